@@ -1,0 +1,43 @@
+"""The CPU oracle against its pins (no GPU)."""
+import numpy as np
+import pytest
+
+import oracle
+from tests import pins
+
+
+@pytest.fixture(scope="module")
+def o():
+    oracle.build()
+    return oracle.Oracle(oracle._LIB_PATH)
+
+
+@pytest.mark.parametrize("pin", pins.ALL_SGEMM_PINS, ids=lambda f: f.__name__)
+def test_sgemm_pin(o, pin):
+    pin(o)
+
+
+def test_bf16_rne_matches_torch(o):
+    pins.pin_bf16_rne_vs_torch(o)
+
+
+def test_bf16x3_split_exhaustive(o):
+    checked, r1, r2 = pins.pin_bf16x3_exhaustive(o)
+    # every finite pattern with 2^-110 <= |x| < 0x1.fep127 (both signs)
+    assert checked > 3_800_000_000
+
+
+def test_bf16x3_method(o):
+    pins.pin_bf16x3_method(o)
+
+
+def test_tolerance_and_metric():
+    assert oracle.tol(4096) == 2 * 4096 * 2.0 ** -24
+    assert oracle.tol(1) == 4 * 2.0 ** -24  # k + 3 dominates at tiny k
+    assert oracle.tol(0) == 3 * 2.0 ** -24
+    cref = np.array([1.0, 0.0, 0.0, 2.0])
+    den = np.array([1.0, 0.0, 0.0, 1.0])
+    e = oracle.normalized_error(np.array([1.0 + 2 ** -20, 0.0, -0.0, np.nan]), cref, den)
+    assert e[0] == 2 ** -20 and e[1] == 0 and e[2] == 0 and np.isinf(e[3])
+    e = oracle.normalized_error(np.array([1.0, 1e-30, 0.0, 2.0]), cref, den)
+    assert np.isinf(e[1])
