@@ -1,0 +1,208 @@
+/*
+ * misgemm: single-precision GEMM for one AMD Instinct MI355X (gfx950).
+ *
+ * The operation is the BLAS sgemm that the paper's BLIS-generated library
+ * solves (Section III-A):
+ *
+ *     C = alpha * op(A) * op(B) + beta * C,    op(X) = X or X^T,
+ *
+ * with op(A) M x K, op(B) K x N and C M x N, every matrix stored column-major
+ * (element (r, c) of a matrix with leading dimension ld at offset r + c*ld),
+ * M, N and K arbitrary.  The argument order is the classic Fortran BLAS one
+ * that the paper's library also generates.
+ *
+ * Memory and streams.  A, B and C are device pointers on the current HIP
+ * device; the caller allocates and owns them, the library never frees them.
+ * A and B are read only; C is read (when beta != 0) and written.  C must not
+ * overlap A or B (not checked).  Rows r in [M, ldc) of C are never written.
+ * `stream` is a hipStream_t passed as void* (NULL = the null stream); every
+ * call is asynchronous on it and returns once the work is enqueued.
+ *
+ * Error convention (every entry point returns int):
+ *   0                  success;
+ *   < 0                invalid argument, numbered by its position in the
+ *                      call, as BLAS xerbla does (-1 = first argument);
+ *                      nothing is launched and C is untouched;
+ *   1 .. 999           a HIP runtime error code (hipError_t);
+ *   >= 1000            a library error, see MISGEMM_E_* below.
+ * misgemm_status_string() describes any of them.
+ *
+ * Degenerate cases follow the reference BLAS: nothing happens when M == 0 or
+ * N == 0, or when (alpha == 0 or K == 0) and beta == 1; when alpha == 0 or
+ * K == 0, A and B are not read and C = beta * C; when beta == 0, C is not
+ * read (NaN or Inf in it does not propagate) and C = alpha * op(A) * op(B).
+ */
+#ifndef MISGEMM_H
+#define MISGEMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Arithmetic forms. */
+typedef enum {
+    /* FP32 matrix-core products (v_mfma_f32_32x32x2_f32), FP32 accumulate. */
+    MISGEMM_FP32 = 0,
+    /* Split precision: each FP32 operand is written as the sum of three
+     * bfloat16 values (round to nearest even, each part rounding what the
+     * previous parts left), the six part products whose part indices sum to
+     * at most 2 run on BF16 matrix cores with FP32 accumulation, and the
+     * result is returned in FP32.  Defined for finite inputs of magnitude
+     * below 0x1.fefp127 (the bf16 overflow threshold); tiny inputs (below
+     * about 2^-110) lose the exactness of the split. */
+    MISGEMM_BF16X3 = 1
+} misgemm_mode;
+
+/* Library error codes (>= 1000). */
+#define MISGEMM_E_NO_DEVICE        1000 /* no gfx950 device is current          */
+#define MISGEMM_E_BAD_CONFIG       1001 /* config id unknown or not for mode     */
+#define MISGEMM_E_CAPTURING        1002 /* call not allowed during graph capture */
+#define MISGEMM_E_TUNING_FILE      1003 /* tuning file unreadable or malformed   */
+#define MISGEMM_E_BATCH            1004 /* bad batch (see bad_index)             */
+#define MISGEMM_E_NULL_PLAN        1005 /* plan pointer is NULL                  */
+#define MISGEMM_E_TOO_LARGE        1006 /* a size exceeds what the kernels index */
+
+/*
+ * C = alpha * op(A) * op(B) + beta * C  (Section III-A).
+ *
+ * transa, transb: 'N'/'n' (op(X) = X) or 'T'/'t'/'C'/'c' (op(X) = X^T; C and
+ *   T coincide for real data, as the paper's test parameters c/h do).
+ * m, n, k >= 0.  A is m x k (transa = N) or k x m (T), lda >= max(1, rows of
+ *   stored A); likewise B is k x n or n x k with ldb; ldc >= max(1, m).
+ * mode: a misgemm_mode.
+ * Errors: -1 transa, -2 transb, -3 m, -4 n, -5 k, -7 A NULL with work to do,
+ *   -8 lda, -9 B NULL, -10 ldb, -12 C NULL, -13 ldc, -14 mode.
+ * The kernel configuration (tile shape, wave layout) comes from the loaded
+ * tuning table when it holds an entry for the shape, else from built-in
+ * heuristics.  Allocates nothing.
+ */
+int misgemm_sgemm(char transa, char transb, int64_t m, int64_t n, int64_t k,
+                  float alpha, const float *A, int64_t lda,
+                  const float *B, int64_t ldb,
+                  float beta, float *C, int64_t ldc,
+                  int mode, void *stream);
+
+/*
+ * misgemm_sgemm with an explicit kernel configuration (an index below
+ * misgemm_num_configs(); the config's mode must equal `mode`).  Used by the
+ * autotuner to time every candidate.  Errors as misgemm_sgemm, plus -15 for
+ * an unknown config id or one of another mode.
+ */
+int misgemm_sgemm_config(char transa, char transb, int64_t m, int64_t n, int64_t k,
+                         float alpha, const float *A, int64_t lda,
+                         const float *B, int64_t ldb,
+                         float beta, float *C, int64_t ldc,
+                         int mode, int config_id, void *stream);
+
+/* Description of one compiled kernel configuration. */
+typedef struct {
+    int mode;          /* misgemm_mode                                  */
+    int bm, bn, bk;    /* workgroup tile: rows of C, columns of C, K step */
+    int wm, wn;        /* per-wave tile of C                            */
+    int threads;       /* threads per workgroup (64 per wave)           */
+    int lds_bytes;     /* LDS used per workgroup                        */
+    char name[48];     /* e.g. "fp32_256x256x16_w128x64"               */
+} misgemm_config_desc;
+
+/* Number of compiled configurations (ids 0 .. n-1). */
+int misgemm_num_configs(void);
+
+/* Fills *out for config `id`; -1 if id is out of range, -2 if out is NULL. */
+int misgemm_config_info(int id, misgemm_config_desc *out);
+
+/*
+ * Which configuration misgemm_sgemm would pick for this problem (tuning
+ * table first, then heuristics), or a negative argument error.
+ */
+int misgemm_select_config(char transa, char transb, int64_t m, int64_t n, int64_t k,
+                          int mode);
+
+/*
+ * Load the tuning table (JSON written by the autotuner) that maps
+ * (mode, transposes, m, n, k) to a config name.  path == NULL clears it and
+ * returns to the built-in heuristics.  Not thread-safe with concurrent
+ * misgemm_sgemm calls.  Error: MISGEMM_E_TUNING_FILE.
+ */
+int misgemm_load_tuning(const char *path);
+
+/* ---------------------------------------------------------------------------
+ * Batched form: many independent sgemm problems in one persistent launch.
+ * ------------------------------------------------------------------------- */
+
+/* One problem of a batch; fields as in misgemm_sgemm. */
+typedef struct {
+    char transa, transb;
+    int64_t m, n, k;
+    float alpha;
+    const float *A;
+    int64_t lda;
+    const float *B;
+    int64_t ldb;
+    float beta;
+    float *C;
+    int64_t ldc;
+} misgemm_problem;
+
+typedef struct misgemm_batch misgemm_batch; /* opaque plan */
+
+/*
+ * Validate `count` problems, cut every one into C tiles of the chosen
+ * configuration, order the tiles by decreasing work (longest first), and
+ * upload the problem and tile tables to device memory owned by the plan.
+ * config_id < 0 picks the configuration from the tuning table / heuristics.
+ * On a bad problem returns that problem's argument error (negative, as for
+ * misgemm_sgemm) or MISGEMM_E_BATCH and stores its index in *bad_index.
+ * Allocates device memory and synchronizes: NOT capturable (returns
+ * MISGEMM_E_CAPTURING if the current device's null stream is capturing).
+ * The pointers inside the problems are stored, not copied: the buffers must
+ * stay valid while the plan is launched.
+ */
+int misgemm_batch_plan(const misgemm_problem *problems, int64_t count, int mode,
+                       int config_id, misgemm_batch **plan, int64_t *bad_index);
+
+/*
+ * Run every problem of the plan in one persistent kernel launch on `stream`.
+ * Allocates nothing and does not synchronize, so it may be captured into a
+ * HIP graph and replayed.  Launches of one plan on several streams at once
+ * race on the plan's C buffers only.
+ */
+int misgemm_batch_launch(const misgemm_batch *plan, void *stream);
+
+/* Plan facts: tiles, workgroups launched, config id, total flops 2*m*n*k. */
+typedef struct {
+    int64_t count, tiles, grid;
+    int config_id;
+    double flops;
+    double tile_flops; /* flops of whole tiles, edges padded (>= flops) */
+} misgemm_batch_desc;
+
+int misgemm_batch_info(const misgemm_batch *plan, misgemm_batch_desc *out);
+
+/* Free the plan's device tables (synchronizes the device first). */
+int misgemm_batch_destroy(misgemm_batch *plan);
+
+/* ---------------------------------------------------------------------------
+ * The split used by MISGEMM_BF16X3, exposed on its own.
+ * ------------------------------------------------------------------------- */
+
+/*
+ * parts[3*i + t] = bit pattern of the t-th bf16 part of x[i], i < count:
+ * part 0 = bf16_rne(x), part 1 = bf16_rne(x - part0), part 2 =
+ * bf16_rne(x - part0 - part1), residuals formed in FP32.  x and parts are
+ * device pointers.  Errors: -1 x NULL, -2 count < 0, -3 parts NULL.
+ */
+int misgemm_bf16x3_split(const float *x, int64_t count, uint16_t *parts, void *stream);
+
+/* Human-readable description of a status code. */
+const char *misgemm_status_string(int status);
+
+/* Library version string. */
+const char *misgemm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MISGEMM_H */

@@ -1,1 +1,242 @@
-"""MI355X-native single-precision GEMM (the BLAS sgemm hot path)."""
+"""MI355X-native single-precision GEMM: the BLAS sgemm hot path.
+
+A thin ``ctypes`` binding of libmisgemm.so (include/misgemm.h).  Every entry
+point keeps its C name without the ``misgemm_`` prefix and only marshals
+arguments: device pointers come from torch tensors (or plain integers), the
+stream defaults to torch's current stream, and a nonzero status raises
+MisgemmError.  All arithmetic runs in the library's HIP kernels; there is no
+fallback of any kind, and a missing library raises on first use.
+
+Matrices are column-major storage buffers: a rows x cols matrix with leading
+dimension ld is a float32 device tensor of ld * cols elements whose element
+(r, c) sits at r + c * ld.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+__all__ = ["MisgemmError", "FP32", "BF16X3", "sgemm", "sgemm_config", "num_configs",
+           "config_info", "configs", "select_config", "load_tuning", "Batch", "bf16x3_split",
+           "status_string", "version", "library_path"]
+
+FP32 = 0
+BF16X3 = 1
+MODES = {"fp32": FP32, "bf16x3": BF16X3}
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libmisgemm.so")
+_lib = None
+
+
+class MisgemmError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__("%s: %s (status %d)" % (where, status_string(status), status))
+
+
+class ConfigDesc(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int), ("bm", ctypes.c_int), ("bn", ctypes.c_int),
+                ("bk", ctypes.c_int), ("wm", ctypes.c_int), ("wn", ctypes.c_int),
+                ("threads", ctypes.c_int), ("lds_bytes", ctypes.c_int),
+                ("name", ctypes.c_char * 48)]
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("transa", ctypes.c_char), ("transb", ctypes.c_char),
+                ("m", ctypes.c_int64), ("n", ctypes.c_int64), ("k", ctypes.c_int64),
+                ("alpha", ctypes.c_float), ("A", ctypes.c_void_p), ("lda", ctypes.c_int64),
+                ("B", ctypes.c_void_p), ("ldb", ctypes.c_int64), ("beta", ctypes.c_float),
+                ("C", ctypes.c_void_p), ("ldc", ctypes.c_int64)]
+
+
+class BatchDesc(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int64), ("tiles", ctypes.c_int64), ("grid", ctypes.c_int64),
+                ("config_id", ctypes.c_int), ("flops", ctypes.c_double),
+                ("tile_flops", ctypes.c_double)]
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError("libmisgemm.so is not built (%s); run "
+                           "`python -m paper_1608_05265_amd.build` first" % _LIB_PATH)
+    lib = ctypes.CDLL(_LIB_PATH)
+    c, i64, f32, i32, vp = ctypes.c_char, ctypes.c_int64, ctypes.c_float, ctypes.c_int, \
+        ctypes.c_void_p
+    sig = [c, c, i64, i64, i64, f32, vp, i64, vp, i64, f32, vp, i64, i32]
+    lib.misgemm_sgemm.argtypes = sig + [vp]
+    lib.misgemm_sgemm.restype = i32
+    lib.misgemm_sgemm_config.argtypes = sig + [i32, vp]
+    lib.misgemm_sgemm_config.restype = i32
+    lib.misgemm_num_configs.argtypes = []
+    lib.misgemm_num_configs.restype = i32
+    lib.misgemm_config_info.argtypes = [i32, ctypes.POINTER(ConfigDesc)]
+    lib.misgemm_config_info.restype = i32
+    lib.misgemm_select_config.argtypes = [c, c, i64, i64, i64, i32]
+    lib.misgemm_select_config.restype = i32
+    lib.misgemm_load_tuning.argtypes = [ctypes.c_char_p]
+    lib.misgemm_load_tuning.restype = i32
+    lib.misgemm_batch_plan.argtypes = [ctypes.POINTER(Problem), i64, i32, i32,
+                                       ctypes.POINTER(vp), ctypes.POINTER(i64)]
+    lib.misgemm_batch_plan.restype = i32
+    lib.misgemm_batch_launch.argtypes = [vp, vp]
+    lib.misgemm_batch_launch.restype = i32
+    lib.misgemm_batch_info.argtypes = [vp, ctypes.POINTER(BatchDesc)]
+    lib.misgemm_batch_info.restype = i32
+    lib.misgemm_batch_destroy.argtypes = [vp]
+    lib.misgemm_batch_destroy.restype = i32
+    lib.misgemm_bf16x3_split.argtypes = [vp, i64, vp, vp]
+    lib.misgemm_bf16x3_split.restype = i32
+    lib.misgemm_status_string.argtypes = [i32]
+    lib.misgemm_status_string.restype = ctypes.c_char_p
+    lib.misgemm_version.argtypes = []
+    lib.misgemm_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _ptr(x) -> Optional[int]:
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _mode(mode) -> int:
+    return MODES[mode] if isinstance(mode, str) else int(mode)
+
+
+def _check(rc: int, where: str) -> None:
+    if rc != 0:
+        raise MisgemmError(rc, where)
+
+
+def status_string(status: int) -> str:
+    return _load().misgemm_status_string(status).decode()
+
+
+def version() -> str:
+    return _load().misgemm_version().decode()
+
+
+def sgemm(transa: str, transb: str, m: int, n: int, k: int, alpha: float, A, lda: int, B,
+          ldb: int, beta: float, C, ldc: int, mode=FP32, stream=None) -> None:
+    """C = alpha * op(A) * op(B) + beta * C (asynchronous on `stream`)."""
+    rc = _load().misgemm_sgemm(transa.encode(), transb.encode(), m, n, k, alpha, _ptr(A), lda,
+                               _ptr(B), ldb, beta, _ptr(C), ldc, _mode(mode), _stream(stream))
+    _check(rc, "misgemm_sgemm")
+
+
+def sgemm_config(transa: str, transb: str, m: int, n: int, k: int, alpha: float, A, lda: int,
+                 B, ldb: int, beta: float, C, ldc: int, mode, config_id: int,
+                 stream=None) -> None:
+    """sgemm with an explicit kernel configuration id."""
+    rc = _load().misgemm_sgemm_config(transa.encode(), transb.encode(), m, n, k, alpha, _ptr(A),
+                                      lda, _ptr(B), ldb, beta, _ptr(C), ldc, _mode(mode),
+                                      config_id, _stream(stream))
+    _check(rc, "misgemm_sgemm_config")
+
+
+def num_configs() -> int:
+    return _load().misgemm_num_configs()
+
+
+def config_info(config_id: int) -> dict:
+    d = ConfigDesc()
+    _check(_load().misgemm_config_info(config_id, ctypes.byref(d)), "misgemm_config_info")
+    return {"id": config_id, "mode": d.mode, "bm": d.bm, "bn": d.bn, "bk": d.bk, "wm": d.wm,
+            "wn": d.wn, "threads": d.threads, "lds_bytes": d.lds_bytes,
+            "name": d.name.decode()}
+
+
+def configs(mode=None) -> List[dict]:
+    out = [config_info(i) for i in range(num_configs())]
+    if mode is not None:
+        out = [c for c in out if c["mode"] == _mode(mode)]
+    return out
+
+
+def select_config(transa: str, transb: str, m: int, n: int, k: int, mode=FP32) -> int:
+    rc = _load().misgemm_select_config(transa.encode(), transb.encode(), m, n, k, _mode(mode))
+    if rc < 0:
+        raise MisgemmError(rc, "misgemm_select_config")
+    return rc
+
+
+def load_tuning(path: Optional[str]) -> None:
+    rc = _load().misgemm_load_tuning(None if path is None else path.encode())
+    _check(rc, "misgemm_load_tuning")
+
+
+def bf16x3_split(x, count: int, parts, stream=None) -> None:
+    """parts[3*i + t] = bit pattern of the t-th bf16 part of x[i]."""
+    rc = _load().misgemm_bf16x3_split(_ptr(x), count, _ptr(parts), _stream(stream))
+    _check(rc, "misgemm_bf16x3_split")
+
+
+class Batch:
+    """A batched plan (misgemm_batch_plan ... misgemm_batch_destroy).
+
+    problems: sequence of dicts or tuples with the misgemm_problem fields
+    (transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc); A, B, C
+    are device tensors or integer device pointers and must outlive the plan.
+    """
+
+    def __init__(self, problems: Sequence, mode=FP32, config_id: int = -1):
+        lib = _load()
+        arr = (Problem * max(1, len(problems)))()
+        for i, p in enumerate(problems):
+            if isinstance(p, dict):
+                p = (p["transa"], p["transb"], p["m"], p["n"], p["k"], p["alpha"], p["A"],
+                     p["lda"], p["B"], p["ldb"], p["beta"], p["C"], p["ldc"])
+            ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc = p
+            arr[i] = Problem(ta.encode(), tb.encode(), m, n, k, alpha, _ptr(A), lda, _ptr(B),
+                             ldb, beta, _ptr(C), ldc)
+        self._keep = problems
+        handle = ctypes.c_void_p()
+        bad = ctypes.c_int64(-1)
+        rc = lib.misgemm_batch_plan(arr, len(problems), _mode(mode), config_id,
+                                    ctypes.byref(handle), ctypes.byref(bad))
+        if rc != 0:
+            err = MisgemmError(rc, "misgemm_batch_plan")
+            err.bad_index = bad.value
+            raise err
+        self._h = handle
+
+    def launch(self, stream=None) -> None:
+        _check(_load().misgemm_batch_launch(self._h, _stream(stream)), "misgemm_batch_launch")
+
+    def info(self) -> dict:
+        d = BatchDesc()
+        _check(_load().misgemm_batch_info(self._h, ctypes.byref(d)), "misgemm_batch_info")
+        return {"count": d.count, "tiles": d.tiles, "grid": d.grid, "config_id": d.config_id,
+                "flops": d.flops, "tile_flops": d.tile_flops}
+
+    def destroy(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value is not None:
+            _check(_load().misgemm_batch_destroy(self._h), "misgemm_batch_destroy")
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

@@ -1,0 +1,495 @@
+// The C-ABI of the library: argument checking, degenerate cases, choice of
+// tile configuration, and the batched plan (see include/misgemm.h).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "registry.hpp"
+
+using namespace misgemm;
+
+namespace {
+
+std::vector<ConfigEntry> &configs()
+{
+    static std::vector<ConfigEntry> table;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        register_f32(table);
+        register_x3(table);
+    });
+    return table;
+}
+
+// Per-device facts, read once per device.
+struct DeviceInfo {
+    bool checked = false;
+    bool ok = false;
+    int cus = 0;
+};
+
+constexpr int MAX_DEVICES = 64;
+DeviceInfo g_devices[MAX_DEVICES];
+std::mutex g_dev_mutex;
+
+int current_device(DeviceInfo **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return MISGEMM_E_NO_DEVICE;
+    if (dev < 0 || dev >= MAX_DEVICES) return MISGEMM_E_NO_DEVICE;
+    std::lock_guard<std::mutex> lock(g_dev_mutex);
+    DeviceInfo &d = g_devices[dev];
+    if (!d.checked) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return MISGEMM_E_NO_DEVICE;
+        d.ok = strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+        d.cus = prop.multiProcessorCount;
+        d.checked = true;
+    }
+    if (!d.ok) return MISGEMM_E_NO_DEVICE;
+    *out = &d;
+    return 0;
+}
+
+int trans_flag(char t)
+{
+    if (t == 'N' || t == 'n') return 0;
+    if (t == 'T' || t == 't' || t == 'C' || t == 'c') return 1;
+    return -1;
+}
+
+// ---------------------------------------------------------------------------
+// Tuning table: lines "mode transa transb m n k config_name" after the
+// header line "misgemm-tuning 1".
+// ---------------------------------------------------------------------------
+struct TuneEntry {
+    int mode, ta, tb;
+    int64_t m, n, k;
+    int config;
+};
+std::vector<TuneEntry> g_tuning;
+std::mutex g_tune_mutex;
+
+int find_config(const char *name)
+{
+    const auto &t = configs();
+    for (size_t i = 0; i < t.size(); ++i)
+        if (strcmp(t[i].desc.name, name) == 0) return (int)i;
+    return -1;
+}
+
+int tuned_config(int mode, int ta, int tb, int64_t m, int64_t n, int64_t k)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    int best = -1;
+    double best_d = 1e300;
+    for (const TuneEntry &e : g_tuning) {
+        if (e.mode != mode || e.ta != ta || e.tb != tb) continue;
+        const double dm = fabs(log2((double)m / (double)e.m));
+        const double dn = fabs(log2((double)n / (double)e.n));
+        const double dk = fabs(log2((double)k / (double)e.k));
+        if (dm > 1.0 || dn > 1.0 || dk > 1.0) continue;  // only within a factor 2
+        const double d = dm + dn + dk;
+        if (d < best_d) { best_d = d; best = e.config; }
+    }
+    return best;
+}
+
+// Built-in choice: the largest tile that still gives every CU at least one
+// tile; below that the smallest tile (fewest idle CUs).
+int heuristic_config(int mode, int64_t m, int64_t n, int64_t k, int cus)
+{
+    (void)k;
+    const auto &t = configs();
+    int best = -1;
+    int64_t best_area = -1;
+    int smallest = -1;
+    int64_t smallest_area = INT64_MAX;
+    for (size_t i = 0; i < t.size(); ++i) {
+        const misgemm_config_desc &d = t[i].desc;
+        if (d.mode != mode) continue;
+        const int64_t area = (int64_t)d.bm * d.bn;
+        const int64_t tiles = ((m + d.bm - 1) / d.bm) * ((n + d.bn - 1) / d.bn);
+        if (tiles >= cus && area > best_area) { best_area = area; best = (int)i; }
+        if (area < smallest_area) { smallest_area = area; smallest = (int)i; }
+    }
+    return best >= 0 ? best : smallest;
+}
+
+int select_config(int mode, int ta, int tb, int64_t m, int64_t n, int64_t k, int cus)
+{
+    const int c = tuned_config(mode, ta, tb, m, n, k);
+    if (c >= 0) return c;
+    return heuristic_config(mode, m, n, k, cus);
+}
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+int validate(char transa, char transb, int64_t m, int64_t n, int64_t k, float alpha,
+             const float *A, int64_t lda, const float *B, int64_t ldb, float *C, int64_t ldc,
+             int mode)
+{
+    const int ta = trans_flag(transa), tb = trans_flag(transb);
+    if (ta < 0) return -1;
+    if (tb < 0) return -2;
+    if (m < 0) return -3;
+    if (n < 0) return -4;
+    if (k < 0) return -5;
+    const int64_t arows = ta ? k : m, brows = tb ? n : k;
+    if (lda < std::max<int64_t>(1, arows)) return -8;
+    if (ldb < std::max<int64_t>(1, brows)) return -10;
+    if (ldc < std::max<int64_t>(1, m)) return -13;
+    if (mode != MISGEMM_FP32 && mode != MISGEMM_BF16X3) return -14;
+    const bool work = m > 0 && n > 0;
+    const bool reads_ab = work && k > 0 && alpha != 0.0f;
+    if (reads_ab && A == nullptr) return -7;
+    if (reads_ab && B == nullptr) return -9;
+    if (work && C == nullptr) return -12;
+    // tile indices are 32-bit in the grid; offsets are 64-bit everywhere
+    if (m > (int64_t)1 << 40 || n > (int64_t)1 << 40 || k > (int64_t)1 << 40)
+        return MISGEMM_E_TOO_LARGE;
+    return 0;
+}
+
+GemmArgs make_args(int64_t m, int64_t n, int64_t k, float alpha, const float *A, int64_t lda,
+                   const float *B, int64_t ldb, float beta, float *C, int64_t ldc)
+{
+    GemmArgs g;
+    g.m = m; g.n = n; g.k = k;
+    g.A = A; g.B = B; g.C = C;
+    g.lda = lda; g.ldb = ldb; g.ldc = ldc;
+    g.alpha = alpha; g.beta = beta;
+    g.vec_a = aligned16(A) && lda % 4 == 0;
+    g.vec_b = aligned16(B) && ldb % 4 == 0;
+    g.vec_c = aligned16(C) && ldc % 4 == 0;
+    return g;
+}
+
+int run_sgemm(char transa, char transb, int64_t m, int64_t n, int64_t k, float alpha,
+              const float *A, int64_t lda, const float *B, int64_t ldb, float beta, float *C,
+              int64_t ldc, int mode, int config_id, void *stream)
+{
+    int rc = validate(transa, transb, m, n, k, alpha, A, lda, B, ldb, C, ldc, mode);
+    if (rc != 0) return rc;
+    const auto &table = configs();
+    if (config_id >= 0 &&
+        (config_id >= (int)table.size() || table[config_id].desc.mode != mode))
+        return -15;
+    if (m == 0 || n == 0) return 0;
+    if ((alpha == 0.0f || k == 0) && beta == 1.0f) return 0;
+    DeviceInfo *dev = nullptr;
+    rc = current_device(&dev);
+    if (rc != 0) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if (alpha == 0.0f || k == 0) return (int)launch_scale(beta, C, m, n, ldc, s);
+    const int ta = trans_flag(transa), tb = trans_flag(transb);
+    const int cfg = config_id >= 0 ? config_id : select_config(mode, ta, tb, m, n, k, dev->cus);
+    if (cfg < 0) return MISGEMM_E_BAD_CONFIG;
+    const misgemm_config_desc &d = table[cfg].desc;
+    const int64_t tiles = ((m + d.bm - 1) / d.bm) * ((n + d.bn - 1) / d.bn);
+    if (tiles > INT32_MAX) return MISGEMM_E_TOO_LARGE;
+    const GemmArgs g = make_args(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+    return (int)table[cfg].launch[ta][tb](g, s);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Batched plan.
+// ---------------------------------------------------------------------------
+struct misgemm_batch {
+    int config_id;
+    int mode;
+    int64_t count, ntiles;
+    int grid;
+    double flops, tile_flops;
+    ProbDev *d_probs;
+    TileDev *d_tiles;
+    int device;
+};
+
+extern "C" {
+
+int misgemm_sgemm(char transa, char transb, int64_t m, int64_t n, int64_t k, float alpha,
+                  const float *A, int64_t lda, const float *B, int64_t ldb, float beta, float *C,
+                  int64_t ldc, int mode, void *stream)
+{
+    return run_sgemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, mode, -1,
+                     stream);
+}
+
+int misgemm_sgemm_config(char transa, char transb, int64_t m, int64_t n, int64_t k, float alpha,
+                         const float *A, int64_t lda, const float *B, int64_t ldb, float beta,
+                         float *C, int64_t ldc, int mode, int config_id, void *stream)
+{
+    if (config_id < 0) return -15;
+    return run_sgemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, mode,
+                     config_id, stream);
+}
+
+int misgemm_num_configs(void) { return (int)configs().size(); }
+
+int misgemm_config_info(int id, misgemm_config_desc *out)
+{
+    if (id < 0 || id >= (int)configs().size()) return -1;
+    if (out == nullptr) return -2;
+    *out = configs()[id].desc;
+    return 0;
+}
+
+int misgemm_select_config(char transa, char transb, int64_t m, int64_t n, int64_t k, int mode)
+{
+    const int ta = trans_flag(transa), tb = trans_flag(transb);
+    if (ta < 0) return -1;
+    if (tb < 0) return -2;
+    if (m < 0) return -3;
+    if (n < 0) return -4;
+    if (k < 0) return -5;
+    if (mode != MISGEMM_FP32 && mode != MISGEMM_BF16X3) return -6;
+    DeviceInfo *dev = nullptr;
+    int cus = 256;
+    if (current_device(&dev) == 0) cus = dev->cus;
+    return select_config(mode, ta, tb, m, n, k, cus);
+}
+
+int misgemm_load_tuning(const char *path)
+{
+    std::vector<TuneEntry> entries;
+    if (path != nullptr) {
+        FILE *f = fopen(path, "r");
+        if (!f) return MISGEMM_E_TUNING_FILE;
+        char line[512];
+        bool header = false;
+        int rc = 0;
+        while (fgets(line, sizeof line, f)) {
+            if (line[0] == '#' || line[0] == '\n') continue;
+            if (!header) {
+                if (strncmp(line, "misgemm-tuning 1", 16) != 0) { rc = MISGEMM_E_TUNING_FILE; break; }
+                header = true;
+                continue;
+            }
+            int mode;
+            char ta, tb;
+            long long m, n, k;
+            char name[64];
+            if (sscanf(line, "%d %c %c %lld %lld %lld %63s", &mode, &ta, &tb, &m, &n, &k, name) != 7 ||
+                m <= 0 || n <= 0 || k <= 0 || trans_flag(ta) < 0 || trans_flag(tb) < 0) {
+                rc = MISGEMM_E_TUNING_FILE;
+                break;
+            }
+            const int id = find_config(name);
+            if (id < 0 || configs()[id].desc.mode != mode) { rc = MISGEMM_E_TUNING_FILE; break; }
+            entries.push_back({mode, trans_flag(ta), trans_flag(tb), m, n, k, id});
+        }
+        fclose(f);
+        if (rc == 0 && !header) rc = MISGEMM_E_TUNING_FILE;
+        if (rc != 0) return rc;
+    }
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    g_tuning.swap(entries);
+    return 0;
+}
+
+int misgemm_batch_plan(const misgemm_problem *problems, int64_t count, int mode, int config_id,
+                       misgemm_batch **plan, int64_t *bad_index)
+{
+    if (bad_index) *bad_index = -1;
+    if (plan == nullptr) return MISGEMM_E_NULL_PLAN;
+    *plan = nullptr;
+    if (count < 0 || (count > 0 && problems == nullptr)) return MISGEMM_E_BATCH;
+    if (mode != MISGEMM_FP32 && mode != MISGEMM_BF16X3) return -14;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(nullptr, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone)
+        return MISGEMM_E_CAPTURING;
+    DeviceInfo *dev = nullptr;
+    int rc = current_device(&dev);
+    if (rc != 0) return rc;
+    const auto &table = configs();
+
+    // configuration: explicit, else the heuristic/tuned choice for the
+    // problem carrying the most work, among configs with a batched variant
+    int cfg = config_id;
+    if (cfg >= 0) {
+        if (cfg >= (int)table.size() || table[cfg].desc.mode != mode || !table[cfg].batch)
+            return MISGEMM_E_BAD_CONFIG;
+    } else {
+        int64_t smallest = INT64_MAX;
+        for (size_t i = 0; i < table.size(); ++i) {
+            const misgemm_config_desc &d = table[i].desc;
+            if (d.mode != mode || !table[i].batch) continue;
+            // default: the 128x128 tile if compiled, else the smallest
+            const int64_t area = (int64_t)d.bm * d.bn;
+            if (d.bm == 128 && d.bn == 128 && cfg < 0) cfg = (int)i;
+            if (area < smallest) smallest = area;
+        }
+        if (cfg < 0)
+            for (size_t i = 0; i < table.size(); ++i)
+                if (table[i].desc.mode == mode && table[i].batch &&
+                    (int64_t)table[i].desc.bm * table[i].desc.bn == smallest) { cfg = (int)i; break; }
+        if (cfg < 0) return MISGEMM_E_BAD_CONFIG;
+    }
+    const misgemm_config_desc &d = table[cfg].desc;
+
+    std::vector<ProbDev> probs;
+    std::vector<TileDev> tiles;
+    std::vector<int64_t> work;  // per-tile K (work of a full tile is bm*bn*k)
+    probs.reserve((size_t)count);
+    double flops = 0.0, tile_flops = 0.0;
+    for (int64_t i = 0; i < count; ++i) {
+        const misgemm_problem &p = problems[i];
+        rc = validate(p.transa, p.transb, p.m, p.n, p.k, p.alpha, p.A, p.lda, p.B, p.ldb, p.C,
+                      p.ldc, mode);
+        if (rc != 0) {
+            if (bad_index) *bad_index = i;
+            return rc;
+        }
+        if (p.m == 0 || p.n == 0) continue;
+        if ((p.alpha == 0.0f || p.k == 0) && p.beta == 1.0f) continue;
+        ProbDev pd;
+        const bool ab = p.alpha != 0.0f && p.k > 0;
+        pd.g = make_args(p.m, p.n, ab ? p.k : 0, p.alpha, p.A, p.lda, p.B, p.ldb, p.beta, p.C,
+                         p.ldc);
+        pd.ta = trans_flag(p.transa);
+        pd.tb = trans_flag(p.transb);
+        pd.tiles_m = (p.m + d.bm - 1) / d.bm;
+        pd.tiles_n = (p.n + d.bn - 1) / d.bn;
+        if (pd.tiles_m > INT32_MAX || pd.tiles_n > INT32_MAX || (int64_t)probs.size() >= INT32_MAX) {
+            if (bad_index) *bad_index = i;
+            return MISGEMM_E_TOO_LARGE;
+        }
+        const int32_t idx = (int32_t)probs.size();
+        probs.push_back(pd);
+        flops += 2.0 * (double)p.m * (double)p.n * (double)pd.g.k;
+        tile_flops += 2.0 * (double)(pd.tiles_m * d.bm) * (double)(pd.tiles_n * d.bn) *
+                      (double)pd.g.k;
+        for (int64_t tn = 0; tn < pd.tiles_n; ++tn)
+            for (int64_t tm = 0; tm < pd.tiles_m; ++tm) {
+                tiles.push_back({idx, (int32_t)tm, (int32_t)tn, 0});
+                work.push_back(pd.g.k);
+            }
+    }
+    // longest-processing-time-first order (stable, so tiles of one problem stay together)
+    std::vector<size_t> order(tiles.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](size_t a, size_t b) { return work[a] > work[b]; });
+    std::vector<TileDev> sorted(tiles.size());
+    for (size_t i = 0; i < order.size(); ++i) sorted[i] = tiles[order[i]];
+
+    misgemm_batch *b = (misgemm_batch *)calloc(1, sizeof(misgemm_batch));
+    if (!b) return (int)hipErrorOutOfMemory;
+    b->config_id = cfg;
+    b->mode = mode;
+    b->count = count;
+    b->ntiles = (int64_t)sorted.size();
+    b->flops = flops;
+    b->tile_flops = tile_flops;
+    hipGetDevice(&b->device);
+    const int occ = table[cfg].batch_occupancy ? table[cfg].batch_occupancy() : 1;
+    int64_t grid = (int64_t)dev->cus * occ;
+    if (grid > b->ntiles) grid = b->ntiles;
+    if (grid < 1) grid = 1;
+    b->grid = (int)grid;
+    hipError_t e = hipSuccess;
+    if (!probs.empty()) {
+        e = hipMalloc((void **)&b->d_probs, probs.size() * sizeof(ProbDev));
+        if (e == hipSuccess) e = hipMalloc((void **)&b->d_tiles, sorted.size() * sizeof(TileDev));
+        if (e == hipSuccess)
+            e = hipMemcpy(b->d_probs, probs.data(), probs.size() * sizeof(ProbDev),
+                          hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(b->d_tiles, sorted.data(), sorted.size() * sizeof(TileDev),
+                          hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+        if (b->d_probs) hipFree(b->d_probs);
+        if (b->d_tiles) hipFree(b->d_tiles);
+        free(b);
+        return (int)e;
+    }
+    *plan = b;
+    return 0;
+}
+
+int misgemm_batch_launch(const misgemm_batch *plan, void *stream)
+{
+    if (plan == nullptr) return MISGEMM_E_NULL_PLAN;
+    if (plan->ntiles == 0) return 0;
+    const ConfigEntry &c = configs()[plan->config_id];
+    return (int)c.batch(plan->d_probs, plan->d_tiles, plan->ntiles, plan->grid,
+                        (hipStream_t)stream);
+}
+
+int misgemm_batch_info(const misgemm_batch *plan, misgemm_batch_desc *out)
+{
+    if (plan == nullptr) return MISGEMM_E_NULL_PLAN;
+    if (out == nullptr) return -2;
+    out->count = plan->count;
+    out->tiles = plan->ntiles;
+    out->grid = plan->grid;
+    out->config_id = plan->config_id;
+    out->flops = plan->flops;
+    out->tile_flops = plan->tile_flops;
+    return 0;
+}
+
+int misgemm_batch_destroy(misgemm_batch *plan)
+{
+    if (plan == nullptr) return MISGEMM_E_NULL_PLAN;
+    hipError_t e = hipDeviceSynchronize();
+    if (plan->d_probs) hipFree(plan->d_probs);
+    if (plan->d_tiles) hipFree(plan->d_tiles);
+    free(plan);
+    return (int)e;
+}
+
+int misgemm_bf16x3_split(const float *x, int64_t count, uint16_t *parts, void *stream)
+{
+    if (x == nullptr && count > 0) return -1;
+    if (count < 0) return -2;
+    if (parts == nullptr && count > 0) return -3;
+    if (count == 0) return 0;
+    DeviceInfo *dev = nullptr;
+    const int rc = current_device(&dev);
+    if (rc != 0) return rc;
+    return (int)launch_split(x, count, parts, (hipStream_t)stream);
+}
+
+const char *misgemm_status_string(int status)
+{
+    static thread_local char buf[160];
+    if (status == 0) return "success";
+    if (status < 0) {
+        snprintf(buf, sizeof buf, "invalid argument at position %d", -status);
+        return buf;
+    }
+    switch (status) {
+    case MISGEMM_E_NO_DEVICE: return "no gfx950 (MI355X) device is current";
+    case MISGEMM_E_BAD_CONFIG: return "unknown kernel configuration for this mode";
+    case MISGEMM_E_CAPTURING: return "call not allowed while a stream is capturing";
+    case MISGEMM_E_TUNING_FILE: return "tuning file unreadable or malformed";
+    case MISGEMM_E_BATCH: return "invalid batch description";
+    case MISGEMM_E_NULL_PLAN: return "batch plan pointer is NULL";
+    case MISGEMM_E_TOO_LARGE: return "a size exceeds the supported range";
+    default: break;
+    }
+    if (status < 1000) {
+        snprintf(buf, sizeof buf, "HIP error %d: %s", status,
+                 hipGetErrorString((hipError_t)status));
+        return buf;
+    }
+    snprintf(buf, sizeof buf, "unknown status %d", status);
+    return buf;
+}
+
+const char *misgemm_version(void) { return "misgemm 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,463 @@
+// Device code of the sgemm path for gfx950 (CDNA4).
+//
+// One workgroup computes one BM x BN tile of C over the whole K range, the
+// GPU form of the paper's blocked scheme (Section III-C): K is consumed in
+// BK-wide blocks, each block of op(A) and op(B) is staged ("packed") from
+// HBM into LDS in one canonical layout that no longer depends on the
+// transposes or leading dimensions, the partial products are accumulated in
+// registers for all of K (the "accumulator" variant of Section III-C), the
+// next block is fetched while the current one is multiplied (the paper's
+// double-buffered input transfer), and alpha/beta are applied once at the
+// end (the post-processing of Section III-C), fused into the store.
+//
+// Two arithmetic forms share the staging/epilogue skeleton:
+//   * F32:    v_mfma_f32_32x32x2_f32, FP32 in, FP32 accumulate.
+//   * BF16X3: every FP32 element is split while it is staged into three
+//             bf16 parts x = x0 + x1 + x2 (round to nearest even), and the six
+//             part products with index sum <= 2 run on
+//             v_mfma_f32_32x32x16_bf16 with FP32 accumulation.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace misgemm {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+
+// Arguments of one GEMM, as seen by a workgroup.
+struct GemmArgs {
+    int64_t m, n, k;
+    const float *A;
+    const float *B;
+    float *C;
+    int64_t lda, ldb, ldc;
+    float alpha, beta;
+    int vec_a, vec_b, vec_c;  // 16-byte vector access legal (aligned base, ld % 4 == 0)
+};
+
+// ---------------------------------------------------------------------------
+// Tile shape: BM x BN per workgroup, BK per K block, WM x WN per wave.
+// ---------------------------------------------------------------------------
+template <int BM_, int BN_, int BK_, int WM_, int WN_>
+struct Shape {
+    static constexpr int BM = BM_, BN = BN_, BK = BK_, WM = WM_, WN = WN_;
+    static constexpr int NWM = BM / WM, NWN = BN / WN, NW = NWM * NWN, NT = 64 * NW;
+    static constexpr int RM = WM / 32, RN = WN / 32;  // 32x32 MFMA blocks per wave
+    static_assert(BM % WM == 0 && BN % WN == 0, "wave tiles must divide the tile");
+    static_assert(WM % 32 == 0 && WN % 32 == 0, "wave tile is made of 32x32 blocks");
+};
+
+// Element (r, kk) of an op(X) tile lives at X[kk + r*ld] when the stored
+// matrix is contiguous along K (KC = true: A transposed, B not transposed)
+// and at X[r + kk*ld] otherwise.
+
+__device__ __forceinline__ floatx4 load4(const float *p, bool vec, bool in_r, int64_t lim_k,
+                                         int64_t step)
+{
+    // Four consecutive elements p[0], p[step], ... masked: element e is read
+    // only when in_r and e < lim_k.  step is 1 for the contiguous direction.
+    floatx4 v;
+    if (vec && in_r && lim_k >= 4) {
+        v = *reinterpret_cast<const floatx4 *>(p);
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = (in_r && e < lim_k) ? p[e * step] : 0.0f;
+    }
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// F32 staging: LDS holds X as Xs[kk][r] (r contiguous, row length LD).
+// ---------------------------------------------------------------------------
+template <int R, int BK, int NT, bool KC>
+struct StageF32 {
+    static constexpr int CH = R * BK / 4;            // float4 chunks per tile
+    static constexpr int S = (CH + NT - 1) / NT;     // chunks per thread
+    static constexpr int LD = R + (KC ? 2 : 4);      // LDS row length (floats)
+    static constexpr int FLOATS = BK * LD;
+    floatx4 v[S];
+
+    __device__ __forceinline__ void chunk(int c, int &r, int &kk) const
+    {
+        if (KC) { kk = (c % (BK / 4)) * 4; r = c / (BK / 4); }
+        else    { r = (c % (R / 4)) * 4;   kk = c / (R / 4); }
+    }
+
+    __device__ __forceinline__ void load(const float *X, int64_t ld, int64_t r0, int64_t k0,
+                                         int64_t rows, int64_t kdim, bool vec, int tid)
+    {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int c = tid + s * NT;
+            if (CH % NT != 0 && c >= CH) break;
+            int r, kk;
+            chunk(c, r, kk);
+            const int64_t gr = r0 + r, gk = k0 + kk;
+            if (KC) {
+                v[s] = load4(X + gk + gr * ld, vec, gr < rows, kdim - gk, 1);
+            } else {
+                // four consecutive rows at one k: rows are the contiguous direction
+                v[s] = load4(X + gr + gk * ld, vec, gk < kdim, rows - gr, 1);
+            }
+        }
+    }
+
+    __device__ __forceinline__ void store(float *Xs, int tid) const
+    {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int c = tid + s * NT;
+            if (CH % NT != 0 && c >= CH) break;
+            int r, kk;
+            chunk(c, r, kk);
+            if (KC) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) Xs[(kk + e) * LD + r] = v[s][e];
+            } else {
+                *reinterpret_cast<floatx4 *>(Xs + kk * LD + r) = v[s];
+            }
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// BF16X3 staging: LDS holds, per part t, Xs[t][r][kk] (kk contiguous, row
+// length LD bf16), so one 16-byte LDS read gives a lane the eight K values
+// a 32x32x16 bf16 MFMA operand needs.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void split3(float x, __bf16 &h0, __bf16 &h1, __bf16 &h2)
+{
+    h0 = (__bf16)x;            // round to nearest even
+    float r = x - (float)h0;   // exact
+    h1 = (__bf16)r;
+    r = r - (float)h1;         // exact
+    h2 = (__bf16)r;
+}
+
+template <int R, int BK, int NT, bool KC>
+struct StageX3 {
+    static constexpr int LD = BK + 8;                  // bf16 per LDS row
+    static constexpr int PART = R * LD;                // bf16 per part
+    static constexpr int HALVES = 3 * PART;            // bf16 per operand tile
+    // KC: a chunk is 4 consecutive k of one row.  !KC: a chunk is a 4 x 4
+    // block (4 rows x 4 k), loaded as 4 row-contiguous float4.
+    static constexpr int CH = KC ? R * BK / 4 : R * BK / 16;
+    static constexpr int S = (CH + NT - 1) / NT;
+    static constexpr int V = KC ? 1 : 4;               // float4 per chunk
+    floatx4 v[S][V];
+
+    __device__ __forceinline__ void chunk(int c, int &r, int &kk) const
+    {
+        if (KC) { kk = (c % (BK / 4)) * 4; r = c / (BK / 4); }
+        else    { r = (c % (R / 4)) * 4;   kk = (c / (R / 4)) * 4; }
+    }
+
+    __device__ __forceinline__ void load(const float *X, int64_t ld, int64_t r0, int64_t k0,
+                                         int64_t rows, int64_t kdim, bool vec, int tid)
+    {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int c = tid + s * NT;
+            if (CH % NT != 0 && c >= CH) break;
+            int r, kk;
+            chunk(c, r, kk);
+            const int64_t gr = r0 + r, gk = k0 + kk;
+            if (KC) {
+                v[s][0] = load4(X + gk + gr * ld, vec, gr < rows, kdim - gk, 1);
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    v[s][q] = load4(X + gr + (gk + q) * ld, vec, gk + q < kdim, rows - gr, 1);
+            }
+        }
+    }
+
+    __device__ __forceinline__ void put(__bf16 *Xs, int r, int kk, float x0, float x1, float x2,
+                                        float x3) const
+    {
+        __bf16 a0, a1, a2, b0, b1, b2, c0, c1, c2, d0, d1, d2;
+        split3(x0, a0, a1, a2);
+        split3(x1, b0, b1, b2);
+        split3(x2, c0, c1, c2);
+        split3(x3, d0, d1, d2);
+        const bf16x4 p0 = {a0, b0, c0, d0}, p1 = {a1, b1, c1, d1}, p2 = {a2, b2, c2, d2};
+        __bf16 *base = Xs + r * LD + kk;
+        *reinterpret_cast<bf16x4 *>(base) = p0;
+        *reinterpret_cast<bf16x4 *>(base + PART) = p1;
+        *reinterpret_cast<bf16x4 *>(base + 2 * PART) = p2;
+    }
+
+    __device__ __forceinline__ void store(__bf16 *Xs, int tid) const
+    {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int c = tid + s * NT;
+            if (CH % NT != 0 && c >= CH) break;
+            int r, kk;
+            chunk(c, r, kk);
+            if (KC) {
+                put(Xs, r, kk, v[s][0][0], v[s][0][1], v[s][0][2], v[s][0][3]);
+            } else {
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr)
+                    put(Xs, r + rr, kk, v[s][0][rr], v[s][1][rr], v[s][2][rr], v[s][3][rr]);
+            }
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Epilogue: C = alpha * acc + beta * C0 for one wave's 32x32 blocks.
+// MFMA 32x32 output layout: lane l, register 4g + e holds row
+// 8g + 4*(l/32) + e, column l % 32, so each lane owns four consecutive rows
+// of one column (one 16-byte store in column-major C).
+// ---------------------------------------------------------------------------
+template <int RM, int RN>
+__device__ __forceinline__ void epilogue(const GemmArgs &g, const floatx16 (&acc)[RM][RN],
+                                         int64_t row0, int64_t col0, int lane)
+{
+    const int half = lane >> 5, l32 = lane & 31;
+    const bool vec = g.vec_c;
+    const bool use_c0 = g.beta != 0.0f;
+#pragma unroll
+    for (int rn = 0; rn < RN; ++rn) {
+        const int64_t col = col0 + rn * 32 + l32;
+        if (col >= g.n) continue;
+        float *cc = g.C + col * g.ldc;
+#pragma unroll
+        for (int rm = 0; rm < RM; ++rm) {
+#pragma unroll
+            for (int gi = 0; gi < 4; ++gi) {
+                const int64_t row = row0 + rm * 32 + gi * 8 + half * 4;
+                if (row >= g.m) continue;
+                float *p = cc + row;
+                floatx4 out;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) out[e] = g.alpha * acc[rm][rn][gi * 4 + e];
+                if (vec && row + 4 <= g.m) {
+                    if (use_c0) {
+                        const floatx4 c0 = *reinterpret_cast<const floatx4 *>(p);
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) out[e] += g.beta * c0[e];
+                    }
+                    *reinterpret_cast<floatx4 *>(p) = out;
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        if (row + e < g.m) {
+                            float o = out[e];
+                            if (use_c0) o += g.beta * p[e];
+                            p[e] = o;
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The tile body: stage -> multiply -> epilogue for tile (m0, n0).
+// ---------------------------------------------------------------------------
+template <class SH, bool TA, bool TB>
+struct F32Tile {
+    using SA = StageF32<SH::BM, SH::BK, SH::NT, TA>;   // A is K-contiguous when transposed
+    using SB = StageF32<SH::BN, SH::BK, SH::NT, !TB>;  // B is K-contiguous when not transposed
+    static constexpr int STAGE_FLOATS = SA::FLOATS + SB::FLOATS;
+    static constexpr int LDS_BYTES = 2 * STAGE_FLOATS * 4;
+    static constexpr int NT = SH::NT;
+
+    __device__ __forceinline__ static void run(const GemmArgs &g, int64_t m0, int64_t n0,
+                                               char *smem)
+    {
+        float *lds = reinterpret_cast<float *>(smem);
+        const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+        const int wm = wave % SH::NWM, wn = wave / SH::NWM;
+        const int half = lane >> 5, l32 = lane & 31;
+
+        floatx16 acc[SH::RM][SH::RN];
+#pragma unroll
+        for (int i = 0; i < SH::RM; ++i)
+#pragma unroll
+            for (int j = 0; j < SH::RN; ++j)
+#pragma unroll
+                for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
+
+        const int64_t ktiles = (g.k + SH::BK - 1) / SH::BK;
+        SA sa;
+        SB sb;
+        if (ktiles > 0) {
+            sa.load(g.A, g.lda, m0, 0, g.m, g.k, g.vec_a, tid);
+            sb.load(g.B, g.ldb, n0, 0, g.n, g.k, g.vec_b, tid);
+            sa.store(lds, tid);
+            sb.store(lds + SA::FLOATS, tid);
+        }
+        __syncthreads();
+        for (int64_t kt = 0; kt < ktiles; ++kt) {
+            float *cur = lds + (kt & 1) * STAGE_FLOATS;
+            float *nxt = lds + ((kt + 1) & 1) * STAGE_FLOATS;
+            const bool more = kt + 1 < ktiles;
+            if (more) {
+                const int64_t k0 = (kt + 1) * SH::BK;
+                sa.load(g.A, g.lda, m0, k0, g.m, g.k, g.vec_a, tid);
+                sb.load(g.B, g.ldb, n0, k0, g.n, g.k, g.vec_b, tid);
+            }
+            const float *As = cur + wm * SH::WM + l32;
+            const float *Bs = cur + SA::FLOATS + wn * SH::WN + l32;
+#pragma unroll
+            for (int ks = 0; ks < SH::BK / 2; ++ks) {
+                const int kr = 2 * ks + half;  // lanes 0-31: even k, 32-63: odd k
+                float a[SH::RM], b[SH::RN];
+#pragma unroll
+                for (int i = 0; i < SH::RM; ++i) a[i] = As[kr * SA::LD + i * 32];
+#pragma unroll
+                for (int j = 0; j < SH::RN; ++j) b[j] = Bs[kr * SB::LD + j * 32];
+#pragma unroll
+                for (int i = 0; i < SH::RM; ++i)
+#pragma unroll
+                    for (int j = 0; j < SH::RN; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[j], acc[i][j],
+                                                                          0, 0, 0);
+            }
+            if (more) {
+                sa.store(nxt, tid);
+                sb.store(nxt + SA::FLOATS, tid);
+            }
+            __syncthreads();
+        }
+        epilogue<SH::RM, SH::RN>(g, acc, m0 + wm * SH::WM, n0 + wn * SH::WN, lane);
+    }
+};
+
+template <class SH, bool TA, bool TB, bool ACC2>
+struct X3Tile {
+    using SA = StageX3<SH::BM, SH::BK, SH::NT, TA>;
+    using SB = StageX3<SH::BN, SH::BK, SH::NT, !TB>;
+    static_assert(SH::BK % 16 == 0, "bf16 MFMA consumes K in steps of 16");
+    static constexpr int STAGE_HALVES = SA::HALVES + SB::HALVES;
+    static constexpr int LDS_BYTES = 2 * STAGE_HALVES * 2;
+    static constexpr int NT = SH::NT;
+
+    __device__ __forceinline__ static void run(const GemmArgs &g, int64_t m0, int64_t n0,
+                                               char *smem)
+    {
+        __bf16 *lds = reinterpret_cast<__bf16 *>(smem);
+        const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+        const int wm = wave % SH::NWM, wn = wave / SH::NWM;
+        const int half = lane >> 5, l32 = lane & 31;
+
+        floatx16 acc[SH::RM][SH::RN];
+        floatx16 lo[ACC2 ? SH::RM : 1][ACC2 ? SH::RN : 1];
+#pragma unroll
+        for (int i = 0; i < SH::RM; ++i)
+#pragma unroll
+            for (int j = 0; j < SH::RN; ++j)
+#pragma unroll
+                for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
+        if (ACC2) {
+#pragma unroll
+            for (int i = 0; i < (ACC2 ? SH::RM : 1); ++i)
+#pragma unroll
+                for (int j = 0; j < (ACC2 ? SH::RN : 1); ++j)
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) lo[i][j][e] = 0.0f;
+        }
+
+        const int64_t ktiles = (g.k + SH::BK - 1) / SH::BK;
+        SA sa;
+        SB sb;
+        if (ktiles > 0) {
+            sa.load(g.A, g.lda, m0, 0, g.m, g.k, g.vec_a, tid);
+            sb.load(g.B, g.ldb, n0, 0, g.n, g.k, g.vec_b, tid);
+            sa.store(lds, tid);
+            sb.store(lds + SA::HALVES, tid);
+        }
+        __syncthreads();
+        for (int64_t kt = 0; kt < ktiles; ++kt) {
+            __bf16 *cur = lds + (kt & 1) * STAGE_HALVES;
+            __bf16 *nxt = lds + ((kt + 1) & 1) * STAGE_HALVES;
+            const bool more = kt + 1 < ktiles;
+            if (more) {
+                const int64_t k0 = (kt + 1) * SH::BK;
+                sa.load(g.A, g.lda, m0, k0, g.m, g.k, g.vec_a, tid);
+                sb.load(g.B, g.ldb, n0, k0, g.n, g.k, g.vec_b, tid);
+            }
+            const __bf16 *As = cur + (wm * SH::WM + l32) * SA::LD + half * 8;
+            const __bf16 *Bs = cur + SA::HALVES + (wn * SH::WN + l32) * SB::LD + half * 8;
+#pragma unroll
+            for (int ks = 0; ks < SH::BK / 16; ++ks) {
+                bf16x8 a[SH::RM][3], b[SH::RN][3];
+#pragma unroll
+                for (int i = 0; i < SH::RM; ++i)
+#pragma unroll
+                    for (int t = 0; t < 3; ++t)
+                        a[i][t] = *reinterpret_cast<const bf16x8 *>(
+                            As + t * SA::PART + i * 32 * SA::LD + ks * 16);
+#pragma unroll
+                for (int j = 0; j < SH::RN; ++j)
+#pragma unroll
+                    for (int t = 0; t < 3; ++t)
+                        b[j][t] = *reinterpret_cast<const bf16x8 *>(
+                            Bs + t * SB::PART + j * 32 * SB::LD + ks * 16);
+#pragma unroll
+                for (int i = 0; i < SH::RM; ++i)
+#pragma unroll
+                    for (int j = 0; j < SH::RN; ++j) {
+                        // smallest terms first; (0,0) is the leading product
+                        floatx16 &small = ACC2 ? lo[ACC2 ? i : 0][ACC2 ? j : 0] : acc[i][j];
+                        small = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][2], small, 0, 0, 0);
+                        small = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][1], b[j][1], small, 0, 0, 0);
+                        small = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][2], b[j][0], small, 0, 0, 0);
+                        small = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][1], small, 0, 0, 0);
+                        small = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][1], b[j][0], small, 0, 0, 0);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][0], acc[i][j], 0, 0, 0);
+                    }
+            }
+            if (more) {
+                sa.store(nxt, tid);
+                sb.store(nxt + SA::HALVES, tid);
+            }
+            __syncthreads();
+        }
+        if (ACC2) {
+#pragma unroll
+            for (int i = 0; i < SH::RM; ++i)
+#pragma unroll
+                for (int j = 0; j < SH::RN; ++j)
+                    acc[i][j] += lo[ACC2 ? i : 0][ACC2 ? j : 0];
+        }
+        epilogue<SH::RM, SH::RN>(g, acc, m0 + wm * SH::WM, n0 + wn * SH::WN, lane);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Tile order: blocks are dispatched round-robin over the 8 XCDs (block b goes
+// to XCD b % 8).  Renumber so that each XCD receives a contiguous range of
+// tile ids, then walk tiles in groups of GROUP_M tile-rows so that the tiles
+// resident on one XCD share A row-panels and B column-panels in its L2.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nb)
+{
+    const int64_t q = nb / 8, r = nb % 8;
+    const int64_t x = bid % 8, idx = bid / 8;
+    const int64_t base = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q;
+    return base + idx;
+}
+
+__device__ __forceinline__ void tile_coords(int64_t t, int64_t tiles_m, int64_t tiles_n,
+                                            int group_m, int64_t &tm, int64_t &tn)
+{
+    const int64_t per_group = (int64_t)group_m * tiles_n;
+    const int64_t grp = t / per_group;
+    const int64_t first_m = grp * group_m;
+    const int64_t gsize = tiles_m - first_m < group_m ? tiles_m - first_m : group_m;
+    const int64_t in_grp = t - grp * per_group;
+    tm = first_m + in_grp % gsize;
+    tn = in_grp / gsize;
+}
+
+}  // namespace misgemm

@@ -1,0 +1,119 @@
+// Kernel entry points and the table of compiled tile configurations.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/misgemm.h"
+#include "gemm_tile.hpp"
+
+namespace misgemm {
+
+// One problem of a batch as the persistent kernel reads it.
+struct ProbDev {
+    GemmArgs g;
+    int32_t ta, tb;
+    int64_t tiles_m, tiles_n;
+};
+
+// One tile of a batch: problem index and tile coordinates.
+struct TileDev {
+    int32_t prob;
+    int32_t tm;
+    int32_t tn;
+    int32_t pad;
+};
+
+typedef hipError_t (*launch_fn)(const GemmArgs &g, hipStream_t s);
+typedef hipError_t (*batch_launch_fn)(const ProbDev *probs, const TileDev *tiles, int64_t ntiles,
+                                      int grid, hipStream_t s);
+typedef int (*occupancy_fn)();
+
+struct ConfigEntry {
+    misgemm_config_desc desc;
+    launch_fn launch[2][2];    // [transa][transb]
+    batch_launch_fn batch;     // NULL when no persistent variant is compiled
+    occupancy_fn batch_occupancy;
+};
+
+constexpr int GROUP_M = 8;
+
+template <class TILE, class SH>
+__global__ __launch_bounds__(SH::NT, 1) void sgemm_kernel(GemmArgs g, int64_t tiles_m,
+                                                          int64_t tiles_n)
+{
+    __shared__ __attribute__((aligned(16))) char smem[TILE::LDS_BYTES];
+    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+    int64_t tm, tn;
+    tile_coords(t, tiles_m, tiles_n, GROUP_M, tm, tn);
+    TILE::run(g, tm * SH::BM, tn * SH::BN, smem);
+}
+
+template <class TILE, class SH>
+hipError_t launch_tile_kernel(const GemmArgs &g, hipStream_t s)
+{
+    const int64_t tm = (g.m + SH::BM - 1) / SH::BM, tn = (g.n + SH::BN - 1) / SH::BN;
+    hipLaunchKernelGGL((sgemm_kernel<TILE, SH>), dim3((unsigned)(tm * tn)), dim3(SH::NT), 0, s,
+                       g, tm, tn);
+    return hipGetLastError();
+}
+
+template <int A, int B>
+struct MaxI { static constexpr int value = A > B ? A : B; };
+
+// Persistent kernel over a list of tiles of many problems.  Workgroup w
+// takes tiles w, w + grid, w + 2*grid, ... of a list sorted by decreasing
+// work, so the longest tiles start first.
+template <template <class, bool, bool> class TILE, class SH>
+__global__ __launch_bounds__(SH::NT, 1) void batch_kernel(const ProbDev *__restrict__ probs,
+                                                          const TileDev *__restrict__ tiles,
+                                                          int64_t ntiles)
+{
+    constexpr int L0 = TILE<SH, false, false>::LDS_BYTES, L1 = TILE<SH, false, true>::LDS_BYTES;
+    constexpr int L2 = TILE<SH, true, false>::LDS_BYTES, L3 = TILE<SH, true, true>::LDS_BYTES;
+    __shared__ __attribute__((aligned(16)))
+    char smem[MaxI<MaxI<L0, L1>::value, MaxI<L2, L3>::value>::value];
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const TileDev td = tiles[t];
+        const ProbDev &p = probs[td.prob];
+        const GemmArgs g = p.g;
+        const int64_t m0 = (int64_t)td.tm * SH::BM, n0 = (int64_t)td.tn * SH::BN;
+        const int sel = p.ta * 2 + p.tb;
+        if (sel == 0) TILE<SH, false, false>::run(g, m0, n0, smem);
+        else if (sel == 1) TILE<SH, false, true>::run(g, m0, n0, smem);
+        else if (sel == 2) TILE<SH, true, false>::run(g, m0, n0, smem);
+        else TILE<SH, true, true>::run(g, m0, n0, smem);
+        __syncthreads();
+    }
+}
+
+template <template <class, bool, bool> class TILE, class SH>
+hipError_t launch_batch_kernel(const ProbDev *probs, const TileDev *tiles, int64_t ntiles,
+                               int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL((batch_kernel<TILE, SH>), dim3(grid), dim3(SH::NT), 0, s, probs, tiles,
+                       ntiles);
+    return hipGetLastError();
+}
+
+template <template <class, bool, bool> class TILE, class SH>
+int batch_occupancy()
+{
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_kernel<TILE, SH>, SH::NT, 0) !=
+        hipSuccess)
+        return 1;
+    return blocks > 0 ? blocks : 1;
+}
+
+// Registration hooks, one per translation unit.
+void register_f32(std::vector<ConfigEntry> &out);
+void register_x3(std::vector<ConfigEntry> &out);
+
+// Host helpers shared by the entry points.
+hipError_t launch_scale(float beta, float *C, int64_t m, int64_t n, int64_t ldc, hipStream_t s);
+hipError_t launch_split(const float *x, int64_t count, uint16_t *parts, hipStream_t s);
+
+}  // namespace misgemm

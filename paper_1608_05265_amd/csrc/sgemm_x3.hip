@@ -1,0 +1,54 @@
+// Split-precision configurations: three bf16 parts per FP32 operand, six
+// part products on v_mfma_f32_32x32x16_bf16, FP32 accumulation.
+#include <string.h>
+
+#include "registry.hpp"
+
+namespace misgemm {
+
+namespace {
+
+// one accumulator for all six products
+template <class SH, bool TA, bool TB>
+using X3S = X3Tile<SH, TA, TB, false>;
+// the leading product a0*b0 in its own accumulator, the five small ones in another
+template <class SH, bool TA, bool TB>
+using X3D = X3Tile<SH, TA, TB, true>;
+
+template <template <class, bool, bool> class T, class SH, bool BATCHED>
+ConfigEntry make_x3(const char *name)
+{
+    ConfigEntry e;
+    memset(&e, 0, sizeof(e));
+    e.desc.mode = MISGEMM_BF16X3;
+    e.desc.bm = SH::BM;
+    e.desc.bn = SH::BN;
+    e.desc.bk = SH::BK;
+    e.desc.wm = SH::WM;
+    e.desc.wn = SH::WN;
+    e.desc.threads = SH::NT;
+    e.desc.lds_bytes = T<SH, false, false>::LDS_BYTES;
+    strncpy(e.desc.name, name, sizeof(e.desc.name) - 1);
+    e.launch[0][0] = launch_tile_kernel<T<SH, false, false>, SH>;
+    e.launch[0][1] = launch_tile_kernel<T<SH, false, true>, SH>;
+    e.launch[1][0] = launch_tile_kernel<T<SH, true, false>, SH>;
+    e.launch[1][1] = launch_tile_kernel<T<SH, true, true>, SH>;
+    if constexpr (BATCHED) {
+        e.batch = launch_batch_kernel<T, SH>;
+        e.batch_occupancy = batch_occupancy<T, SH>;
+    }
+    return e;
+}
+
+}  // namespace
+
+void register_x3(std::vector<ConfigEntry> &out)
+{
+    out.push_back(make_x3<X3S, Shape<256, 256, 16, 128, 128>, false>("x3_256x256x16_w128x128"));
+    out.push_back(make_x3<X3D, Shape<256, 128, 16, 128, 64>, false>("x3d_256x128x16_w128x64"));
+    out.push_back(make_x3<X3S, Shape<128, 128, 32, 64, 64>, true>("x3_128x128x32_w64x64"));
+    out.push_back(make_x3<X3D, Shape<128, 128, 32, 64, 64>, true>("x3d_128x128x32_w64x64"));
+    out.push_back(make_x3<X3S, Shape<64, 64, 32, 32, 32>, true>("x3_64x64x32_w32x32"));
+}
+
+}  // namespace misgemm
