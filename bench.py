@@ -1,0 +1,271 @@
+#!/usr/bin/env python3
+"""Benchmark of the sgemm hot path on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--workload square|c1|rankk|wide|batch]
+
+One step is one pass of the workload's GEMMs over seeded synthetic inputs
+that are already resident in HBM.  The default workload is the square sweep
+M = N = K in {1024, 2048, 4096, 8192} over the four transpose pairs
+(alpha = 1.5, beta = -0.5, every leading dimension padded by 16): sixteen
+sgemm calls per step, run first in native FP32-MFMA form (the line's
+`value`) and then in bf16x3 form (the `bf16x3` object).  TFLOP/s counts
+2*M*N*K per call.
+
+Printed: one JSON line with the metric, the roofline of the dominant kernel
+(timed with HIP events on the stream it runs on), and the CPU oracle timed on
+a bounded sample of the same inputs, which also measures the error of the
+GPU results on that sample against the acceptance bound.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "SGEMM TFLOP/s and % of MFMA peak, native FP32 vs bf16x3 at stated error"
+PEAK_FP32 = 157.3      # TFLOP/s, MI355X dense FP32 matrix (= FP32 vector)
+PEAK_BF16 = 2516.6     # TFLOP/s, MI355X dense BF16 matrix
+PEAK_HBM = 8000.0      # GB/s
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="square",
+                    choices=["square", "c1", "rankk", "wide", "batch"])
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle leg (used under the profiler)")
+    return ap.parse_args()
+
+
+def make_problems(workload):
+    from paper_1608_05265_amd import workloads as wl
+    if workload == "square":
+        return [wl.config2(s, ta, tb) for s in wl.SQUARE_SIZES for ta, tb in wl.TRANS_PAIRS], \
+            "square sweep M=N=K in {1024,2048,4096,8192} x {NN,NT,TN,TT}, alpha=1.5, " \
+            "beta=-0.5, ld=rows+16, uniform[-1,1]"
+    if workload == "c1":
+        return [wl.config1()], "single sgemm 256^3 NN, alpha=1, beta=0, uniform[-1,1]"
+    if workload == "rankk":
+        return [wl.config3(k) for k in wl.RANKK_KS], \
+            "rank-k update M=N=16384, K in {128,256,512}, NN, alpha=-1, beta=1, normal(0,1)"
+    if workload == "wide":
+        return [wl.config4()], "8192^3 NN, alpha=1, beta=0, entries random sign x 2^U[-8,8]"
+    raise ValueError(workload)
+
+
+class Resident:
+    """A problem's operands on the device, C restorable to C0."""
+
+    def __init__(self, p, dev):
+        import torch
+        self.p = p
+        self.A = torch.from_numpy(p.A).to(dev)
+        self.B = torch.from_numpy(p.B).to(dev)
+        self.C0 = torch.from_numpy(p.C0).to(dev)
+        self.C = self.C0.clone()
+
+    def call(self, mg, mode):
+        p = self.p
+        mg.sgemm(p.transa, p.transb, p.m, p.n, p.k, p.alpha, self.A, p.lda, self.B, p.ldb,
+                 p.beta, self.C, p.ldc, mode=mode)
+
+    def reset(self):
+        self.C.copy_(self.C0)
+
+
+def time_steps(torch, res, mg, mode, steps, warmup, dominant):
+    """Run warmup + steps passes; returns (total seconds, dominant-kernel
+    launch durations in ms).  The dominant kernel is timed with events on
+    the stream the library launches on (torch's current stream)."""
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        for r in res:
+            r.call(mg, mode)
+    torch.cuda.synchronize()
+    ev = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for i, r in enumerate(res):
+            if i in dominant:
+                s = torch.cuda.Event(enable_timing=True)
+                e = torch.cuda.Event(enable_timing=True)
+                s.record(stream)
+                r.call(mg, mode)
+                e.record(stream)
+                ev.append((s, e))
+            else:
+                r.call(mg, mode)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    durs = [s.elapsed_time(e) for s, e in ev]
+    return total, durs
+
+
+def cpu_baseline_leg(res, mg, torch, workload):
+    """The FP64 oracle timed on a bounded sample of the same inputs, on the
+    host's cores; the same sample gives the error of the GPU results."""
+    import oracle
+    cores = len(os.sched_getaffinity(0))
+    out = {"kind": "oracle", "cores": cores, "unit": "TFLOP/s"}
+    # the largest problem the full oracle finishes in ~10-30 s of CPU work
+    pick = None
+    for r in res:
+        flops = 2.0 * r.p.m * r.p.n * r.p.k
+        if flops <= 2.0 * 4096 ** 3 and (pick is None or flops > 2.0 * pick.p.m * pick.p.n * pick.p.k):
+            pick = r
+    if pick is None:
+        pick = min(res, key=lambda r: r.p.m * r.p.n * r.p.k)
+    p = pick.p
+    errors = {}
+    for mode, name in ((mg.FP32, "fp32"), (mg.BF16X3, "bf16x3")):
+        pick.reset()
+        pick.call(mg, mode)
+        torch.cuda.synchronize()
+        gpu = pick.C.cpu().numpy()
+        if name == "fp32":
+            t0 = time.perf_counter()
+            cref, den = oracle.sgemm_f64(p.transa, p.transb, p.m, p.n, p.k, p.alpha, p.A, p.lda,
+                                         p.B, p.ldb, p.beta, p.C0, p.ldc, nthreads=cores)
+            dt = time.perf_counter() - t0
+            out["value"] = 2.0 * p.m * p.n * p.k / dt / 1e12
+            out["seconds"] = dt
+            out["sample"] = ("full FP64 oracle (C and |A||B|) of the %dx%dx%d %s%s problem of "
+                             "the workload, same inputs as the GPU run; rate = 2MNK / time"
+                             % (p.m, p.n, p.k, p.transa, p.transb))
+        got = gpu.reshape(p.n, p.ldc).T[:p.m, :]
+        ok, mx, mean, ratio = oracle.check(got, cref, den, p.k)
+        errors[name] = {"problem": p.label, "max_norm_err": mx, "mean_norm_err": mean,
+                        "max_over_bound": ratio, "within_bound": bool(ok)}
+    # sampled entries of every other problem, both forms
+    for r in res:
+        if r is pick:
+            continue
+        q = r.p
+        rng = np.random.default_rng(17)
+        rows = rng.integers(0, q.m, 512)
+        cols = rng.integers(0, q.n, 512)
+        cref_s, den_s = oracle.sgemm_f64_entries(q.transa, q.transb, q.m, q.n, q.k, q.alpha, q.A,
+                                                 q.lda, q.B, q.ldb, q.beta, q.C0, q.ldc, rows,
+                                                 cols, nthreads=cores)
+        for mode, name in ((mg.FP32, "fp32"), (mg.BF16X3, "bf16x3")):
+            r.reset()
+            r.call(mg, mode)
+            torch.cuda.synchronize()
+            got = r.C.cpu().numpy()[rows + cols * q.ldc]
+            ok, mx, mean, ratio = oracle.check(got, cref_s, den_s, q.k)
+            e = errors.setdefault(name + "_sampled", {"max_over_bound": 0.0, "within_bound": True,
+                                                     "entries_per_problem": 512})
+            e["max_over_bound"] = max(e["max_over_bound"], ratio)
+            e["within_bound"] = e["within_bound"] and bool(ok)
+    return out, errors
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_1608_05265_amd as mg
+    dev = torch.device("cuda:0")
+    if args.workload == "batch":
+        from paper_1608_05265_amd import batch_bench
+        print(json.dumps(batch_bench.run(args, METRIC, PEAK_FP32, PEAK_BF16)))
+        return
+    problems, desc = make_problems(args.workload)
+    res = [Resident(p, dev) for p in problems]
+    torch.cuda.synchronize()
+    flops_step = sum(2.0 * r.p.m * r.p.n * r.p.k for r in res)
+    big = max(r.p.m * r.p.n * r.p.k for r in res)
+    dominant = [i for i, r in enumerate(res) if r.p.m * r.p.n * r.p.k == big]
+
+    result = {}
+    for mode, name in ((mg.FP32, "fp32"), (mg.BF16X3, "bf16x3")):
+        total, durs = time_steps(torch, res, mg, mode, args.steps, args.warmup, dominant)
+        dp = res[dominant[0]].p
+        per_launch = 2.0 * dp.m * dp.n * dp.k
+        avg_ms = float(np.mean(durs))
+        result[name] = {"seconds": total, "tflops": flops_step * args.steps / total / 1e12,
+                        "ms_per_step": total / args.steps * 1e3,
+                        "dominant_avg_ms": avg_ms,
+                        "dominant_tflops": per_launch / (avg_ms * 1e-3) / 1e12,
+                        "dominant": "%dx%dx%d (%s)" % (dp.m, dp.n, dp.k,
+                                                       ",".join(res[i].p.transa + res[i].p.transb
+                                                                for i in dominant))}
+    # per-problem rates (one extra timed pass each, after the timed region)
+    per_problem = []
+    for r in res:
+        row = {"problem": r.p.label}
+        for mode, name in ((mg.FP32, "fp32"), (mg.BF16X3, "bf16x3")):
+            s = torch.cuda.Event(enable_timing=True)
+            e = torch.cuda.Event(enable_timing=True)
+            r.call(mg, mode)
+            s.record()
+            reps = 5
+            for _ in range(reps):
+                r.call(mg, mode)
+            e.record()
+            torch.cuda.synchronize()
+            ms = s.elapsed_time(e) / reps
+            row[name + "_tflops"] = round(2.0 * r.p.m * r.p.n * r.p.k / ms / 1e9, 2)
+        per_problem.append(row)
+
+    f32 = result["fp32"]
+    x3 = result["bf16x3"]
+    dp = res[dominant[0]].p
+    line = {
+        "metric": METRIC,
+        "value": round(f32["tflops"], 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(f32["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": desc, "gemms_per_step": len(res),
+                   "flops_per_step": flops_step, "forms": "fp32 (value), bf16x3 (bf16x3 object)"},
+        "pct_of_fp32_peak": round(100.0 * f32["tflops"] / PEAK_FP32, 2),
+        "bf16x3": {"value": round(x3["tflops"], 3), "unit": "TFLOP/s (FP32-equivalent, 2MNK)",
+                   "ms_per_step": round(x3["ms_per_step"], 4),
+                   "pct_of_bf16_mfma_peak": round(100.0 * 6 * x3["tflops"] / PEAK_BF16, 2),
+                   "pct_of_fp32_peak": round(100.0 * x3["tflops"] / PEAK_FP32, 2),
+                   "dominant_tflops": round(x3["dominant_tflops"], 2)},
+        "roofline": {
+            "bound": "mfma",
+            "kernel": "sgemm fp32 tile kernel, %s" % f32["dominant"],
+            "achieved": round(f32["dominant_tflops"], 3),
+            "peak": PEAK_FP32,
+            "unit": "TFLOP/s",
+            "frac": round(f32["dominant_tflops"] / PEAK_FP32, 4),
+            "avg_launch_ms": round(f32["dominant_avg_ms"], 4),
+            "flops_per_launch": 2.0 * dp.m * dp.n * dp.k,
+            "traffic": None,
+        },
+        "per_problem": per_problem,
+    }
+    if not args.no_cpu_baseline:
+        cpu, errors = cpu_baseline_leg(res, mg, torch, args.workload)
+        line["cpu_baseline"] = cpu
+        line["error"] = errors
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()
