@@ -140,72 +140,107 @@ __device__ __forceinline__ void split3(float x, __bf16 &h0, __bf16 &h1, __bf16 &
 
 template <int R, int BK, int NT, bool KC>
 struct StageX3 {
+    // Row stride of 16*(BK/8 + 1) bytes: the 16-byte reads and writes of 32
+    // consecutive rows fall in distinct LDS banks.
     static constexpr int LD = BK + 8;                  // bf16 per LDS row
     static constexpr int PART = R * LD;                // bf16 per part
     static constexpr int HALVES = 3 * PART;            // bf16 per operand tile
-    // KC: a chunk is 4 consecutive k of one row.  !KC: a chunk is a 4 x 4
-    // block (4 rows x 4 k), loaded as 4 row-contiguous float4.
-    static constexpr int CH = KC ? R * BK / 4 : R * BK / 16;
+    // A chunk is eight consecutive k of one row; consecutive threads take
+    // consecutive rows.
+    static constexpr int KS = 8;
+    static constexpr int CH = R * BK / KS;
     static constexpr int S = (CH + NT - 1) / NT;
-    static constexpr int V = KC ? 1 : 4;               // float4 per chunk
-    floatx4 v[S][V];
+    static constexpr bool UNITS_FULL = CH % NT == 0;
+    static constexpr int UNITS = S;
+    float v[S][KS];
 
-    __device__ __forceinline__ void chunk(int c, int &r, int &kk) const
+    __device__ __forceinline__ static void chunk(int c, int &r, int &kk)
     {
-        if (KC) { kk = (c % (BK / 4)) * 4; r = c / (BK / 4); }
-        else    { r = (c % (R / 4)) * 4;   kk = (c / (R / 4)) * 4; }
+        r = c % R;
+        kk = (c / R) * KS;
     }
 
     __device__ __forceinline__ void load(const float *X, int64_t ld, int64_t r0, int64_t k0,
                                          int64_t rows, int64_t kdim, bool vec, int tid)
     {
+        // Interior tiles (uniform across the workgroup) load without masks;
+        // edge tiles mask every element.
+        const bool interior = r0 + R <= rows && k0 + BK <= kdim && (vec || !KC);
+        if (interior) {
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const int c = tid + s * NT;
+                if (!UNITS_FULL && c >= CH) break;
+                int r, kk;
+                chunk(c, r, kk);
+                const int64_t gr = r0 + r, gk = k0 + kk;
+                if (KC) {
+                    const float *p = X + gk + gr * ld;
+                    const floatx4 x0 = *reinterpret_cast<const floatx4 *>(p);
+                    const floatx4 x1 = *reinterpret_cast<const floatx4 *>(p + 4);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) { v[s][e] = x0[e]; v[s][4 + e] = x1[e]; }
+                } else {
+                    const float *p = X + gr + gk * ld;
+#pragma unroll
+                    for (int e = 0; e < KS; ++e) v[s][e] = p[e * ld];
+                }
+            }
+            return;
+        }
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             const int c = tid + s * NT;
-            if (CH % NT != 0 && c >= CH) break;
+            if (!UNITS_FULL && c >= CH) break;
             int r, kk;
             chunk(c, r, kk);
             const int64_t gr = r0 + r, gk = k0 + kk;
+            const bool in_r = gr < rows;
             if (KC) {
-                v[s][0] = load4(X + gk + gr * ld, vec, gr < rows, kdim - gk, 1);
-            } else {
+                const float *p = X + gk + gr * ld;
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    v[s][q] = load4(X + gr + (gk + q) * ld, vec, gk + q < kdim, rows - gr, 1);
+                for (int e = 0; e < KS; ++e) v[s][e] = (in_r && gk + e < kdim) ? p[e] : 0.0f;
+            } else {
+                const float *p = X + gr + gk * ld;
+#pragma unroll
+                for (int e = 0; e < KS; ++e) v[s][e] = (in_r && gk + e < kdim) ? p[e * ld] : 0.0f;
             }
         }
     }
 
-    __device__ __forceinline__ void put(__bf16 *Xs, int r, int kk, float x0, float x1, float x2,
-                                        float x3) const
+    __device__ __forceinline__ float unit_val(int u, int e) const { return v[u][e]; }
+
+    __device__ __forceinline__ static int unit_offset(int u, int tid)
     {
-        __bf16 a0, a1, a2, b0, b1, b2, c0, c1, c2, d0, d1, d2;
-        split3(x0, a0, a1, a2);
-        split3(x1, b0, b1, b2);
-        split3(x2, c0, c1, c2);
-        split3(x3, d0, d1, d2);
-        const bf16x4 p0 = {a0, b0, c0, d0}, p1 = {a1, b1, c1, d1}, p2 = {a2, b2, c2, d2};
-        __bf16 *base = Xs + r * LD + kk;
-        *reinterpret_cast<bf16x4 *>(base) = p0;
-        *reinterpret_cast<bf16x4 *>(base + PART) = p1;
-        *reinterpret_cast<bf16x4 *>(base + 2 * PART) = p2;
+        int r, kk;
+        chunk(tid + u * NT, r, kk);
+        return r * LD + kk;
+    }
+
+    // Split the eight values of unit u and write the three parts.
+    __device__ __forceinline__ void store_unit(__bf16 *Xs, int u, int tid) const
+    {
+        bf16x8 p0, p1, p2;
+#pragma unroll
+        for (int e = 0; e < KS; ++e) {
+            __bf16 h0, h1, h2;
+            split3(v[u][e], h0, h1, h2);
+            p0[e] = h0;
+            p1[e] = h1;
+            p2[e] = h2;
+        }
+        __bf16 *base = Xs + unit_offset(u, tid);
+        *reinterpret_cast<bf16x8 *>(base) = p0;
+        *reinterpret_cast<bf16x8 *>(base + PART) = p1;
+        *reinterpret_cast<bf16x8 *>(base + 2 * PART) = p2;
     }
 
     __device__ __forceinline__ void store(__bf16 *Xs, int tid) const
     {
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            const int c = tid + s * NT;
-            if (CH % NT != 0 && c >= CH) break;
-            int r, kk;
-            chunk(c, r, kk);
-            if (KC) {
-                put(Xs, r, kk, v[s][0][0], v[s][0][1], v[s][0][2], v[s][0][3]);
-            } else {
-#pragma unroll
-                for (int rr = 0; rr < 4; ++rr)
-                    put(Xs, r + rr, kk, v[s][0][rr], v[s][1][rr], v[s][2][rr], v[s][3][rr]);
-            }
+            if (!UNITS_FULL && tid + s * NT >= CH) break;
+            store_unit(Xs, s, tid);
         }
     }
 };
@@ -431,6 +466,203 @@ struct X3Tile {
                     acc[i][j] += lo[ACC2 ? i : 0][ACC2 ? j : 0];
         }
         epilogue<SH::RM, SH::RN>(g, acc, m0 + wm * SH::WM, n0 + wn * SH::WN, lane);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Software-pipelined split-precision tile.  While the matrix cores work on K
+// block kt from LDS, the global loads of block kt+1 are in flight, and once a
+// fraction Q0_NUM/Q0_DEN of the block's MFMA instructions are issued the
+// split and LDS store of block kt+1 are interleaved between the remaining
+// ones.  One workgroup barrier per K block.
+// ---------------------------------------------------------------------------
+template <class SH, bool TA, bool TB, int Q0_NUM = 1, int Q0_DEN = 3, bool FENCED = false>
+struct X3PTile {
+    using SA = StageX3<SH::BM, SH::BK, SH::NT, TA>;
+    using SB = StageX3<SH::BN, SH::BK, SH::NT, !TB>;
+    static_assert(SH::BK == 16, "one bf16 MFMA K step per K block");
+    static_assert(SA::UNITS_FULL && SB::UNITS_FULL, "every thread stages whole units");
+    static constexpr int STAGE_HALVES = SA::HALVES + SB::HALVES;
+    static constexpr int LDS_BYTES = 2 * STAGE_HALVES * 2;
+    static constexpr int NT = SH::NT;
+    static constexpr int RM = SH::RM, RN = SH::RN;
+    static constexpr int NMFMA = RM * RN * 6;
+    static constexpr int NELEM = SA::KS * (SA::UNITS + SB::UNITS);
+    // first MFMA slot that carries split/store work for the next block
+    static constexpr int Q0 = NMFMA * Q0_NUM / Q0_DEN;
+
+    // Split element e (A units first, then B units) of the staged block into
+    // the pending part vectors; after the last element of a unit, write the
+    // unit's three parts to LDS.
+    __device__ __forceinline__ static void split_elem(int e, const SA &sa, const SB &sb,
+                                                      __bf16 *dst, int tid, bf16x8 &p0,
+                                                      bf16x8 &p1, bf16x8 &p2)
+    {
+        constexpr int KS = SA::KS;
+        const int u = e / KS, q = e % KS;
+        __bf16 h0, h1, h2;
+        if (u < SA::UNITS) split3(sa.unit_val(u, q), h0, h1, h2);
+        else split3(sb.unit_val(u - SA::UNITS, q), h0, h1, h2);
+        p0[q] = h0;
+        p1[q] = h1;
+        p2[q] = h2;
+        if (q == KS - 1) {
+            __bf16 *base;
+            int part;
+            if (u < SA::UNITS) { base = dst + SA::unit_offset(u, tid); part = SA::PART; }
+            else { base = dst + SA::HALVES + SB::unit_offset(u - SA::UNITS, tid); part = SB::PART; }
+            *reinterpret_cast<bf16x8 *>(base) = p0;
+            *reinterpret_cast<bf16x8 *>(base + part) = p1;
+            *reinterpret_cast<bf16x8 *>(base + 2 * part) = p2;
+        }
+    }
+
+    template <bool STORE>
+    __device__ __forceinline__ static void body(floatx16 (&acc)[RM][RN], const __bf16 *cur,
+                                                __bf16 *nxt, const SA &sa, const SB &sb,
+                                                int tid, int wm, int wn, int half, int l32)
+    {
+        const __bf16 *As = cur + (wm * SH::WM + l32) * SA::LD + half * 8;
+        const __bf16 *Bs = cur + SA::HALVES + (wn * SH::WN + l32) * SB::LD + half * 8;
+        bf16x8 a[RM][3], b[2][3];
+#pragma unroll
+        for (int i = 0; i < RM; ++i)
+#pragma unroll
+            for (int t = 0; t < 3; ++t)
+                a[i][t] = *reinterpret_cast<const bf16x8 *>(As + t * SA::PART + i * 32 * SA::LD);
+#pragma unroll
+        for (int t = 0; t < 3; ++t)
+            b[0][t] = *reinterpret_cast<const bf16x8 *>(Bs + t * SB::PART);
+        if constexpr (FENCED) {
+            // Explicit order: after slot Q0 every MFMA is followed by the
+            // split of a few elements (and the unit's LDS write when its last
+            // element is done); sched_barrier keeps the compiler from moving
+            // anything across.
+            bf16x8 p0, p1, p2;
+            int q = 0;
+#pragma unroll
+            for (int j = 0; j < RN; ++j) {
+#pragma unroll
+                for (int pr = 0; pr < 6; ++pr) {
+#pragma unroll
+                    for (int i = 0; i < RM; ++i) {
+                        const int sa_i = pr == 0 ? 0 : pr == 1 ? 1 : pr == 2 ? 2 : pr == 3 ? 0 : pr == 4 ? 1 : 0;
+                        const int sb_j = pr == 0 ? 2 : pr == 1 ? 1 : pr == 2 ? 0 : pr == 3 ? 1 : pr == 4 ? 0 : 0;
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                            a[i][sa_i], b[j & 1][sb_j], acc[i][j], 0, 0, 0);
+                        __builtin_amdgcn_sched_barrier(0);
+                        if (i == 0 && pr == 0 && j + 1 < RN) {
+#pragma unroll
+                            for (int t = 0; t < 3; ++t)
+                                b[(j + 1) & 1][t] = *reinterpret_cast<const bf16x8 *>(
+                                    Bs + t * SB::PART + (j + 1) * 32 * SB::LD);
+                            __builtin_amdgcn_sched_barrier(0);
+                        }
+                        if (STORE && q >= Q0) {
+                            const int e0 = (q - Q0) * NELEM / (NMFMA - Q0);
+                            const int e1 = (q + 1 - Q0) * NELEM / (NMFMA - Q0);
+#pragma unroll
+                            for (int e = e0; e < e1; ++e) split_elem(e, sa, sb, nxt, tid, p0, p1, p2);
+                            if (e1 > e0) __builtin_amdgcn_sched_barrier(0);
+                        }
+                        ++q;
+                    }
+                }
+            }
+            return;
+        }
+#pragma unroll
+        for (int j = 0; j < RN; ++j) {
+            // products, smallest first: (0,2) (1,1) (2,0) (0,1) (1,0) (0,0);
+            // consecutive MFMAs go to different accumulators (i varies fastest)
+#pragma unroll
+            for (int pr = 0; pr < 6; ++pr) {
+#pragma unroll
+                for (int i = 0; i < RM; ++i) {
+                    const int sa_i = pr == 0 ? 0 : pr == 1 ? 1 : pr == 2 ? 2 : pr == 3 ? 0 : pr == 4 ? 1 : 0;
+                    const int sb_j = pr == 0 ? 2 : pr == 1 ? 1 : pr == 2 ? 0 : pr == 3 ? 1 : pr == 4 ? 0 : 0;
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][sa_i], b[j & 1][sb_j],
+                                                                         acc[i][j], 0, 0, 0);
+                    if (i == 0 && pr == 0 && j + 1 < RN) {
+#pragma unroll
+                        for (int t = 0; t < 3; ++t)
+                            b[(j + 1) & 1][t] = *reinterpret_cast<const bf16x8 *>(
+                                Bs + t * SB::PART + (j + 1) * 32 * SB::LD);
+                    }
+                }
+            }
+        }
+        if (STORE) {
+#pragma unroll
+            for (int u = 0; u < SA::UNITS; ++u) sa.store_unit(nxt, u, tid);
+#pragma unroll
+            for (int u = 0; u < SB::UNITS; ++u) sb.store_unit(nxt + SA::HALVES, u, tid);
+        }
+        // Issue order: the fragment reads first, then one MFMA at a time;
+        // from MFMA slot Q0 on, each slot also carries a share of the split
+        // (independent VALU work from several elements, so the in-order issue
+        // does not wait on one element's dependency chain) and, every few
+        // slots, one 16-byte LDS write.  B fragments of the next column are
+        // read right after the first MFMA of the current column.
+        constexpr int NWRITE = 3 * (SA::UNITS + SB::UNITS);
+        constexpr int NVALU = 8 * NELEM;  // split work plus address arithmetic
+        constexpr int SLOTS = NMFMA - Q0;
+        constexpr int VPER = (NVALU + SLOTS - 1) / SLOTS;
+        __builtin_amdgcn_sched_group_barrier(0x100, 3 * RM + 3, 0);
+#pragma unroll
+        for (int qq = 0; qq < NMFMA; ++qq) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            if (qq % (6 * RM) == 0 && qq / (6 * RM) + 1 < RN)
+                __builtin_amdgcn_sched_group_barrier(0x100, 3, 0);
+            if (STORE && qq >= Q0) {
+                __builtin_amdgcn_sched_group_barrier(0x002, VPER, 0);
+                if ((qq - Q0) * NWRITE / SLOTS != (qq + 1 - Q0) * NWRITE / SLOTS)
+                    __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+            }
+        }
+    }
+
+    __device__ __forceinline__ static void run(const GemmArgs &g, int64_t m0, int64_t n0,
+                                               char *smem)
+    {
+        __bf16 *lds = reinterpret_cast<__bf16 *>(smem);
+        const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+        const int wm = wave % SH::NWM, wn = wave / SH::NWM;
+        const int half = lane >> 5, l32 = lane & 31;
+
+        floatx16 acc[RM][RN];
+#pragma unroll
+        for (int i = 0; i < RM; ++i)
+#pragma unroll
+            for (int j = 0; j < RN; ++j)
+#pragma unroll
+                for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
+
+        const int64_t ktiles = (g.k + SH::BK - 1) / SH::BK;
+        SA sa;
+        SB sb;
+        if (ktiles > 0) {
+            sa.load(g.A, g.lda, m0, 0, g.m, g.k, g.vec_a, tid);
+            sb.load(g.B, g.ldb, n0, 0, g.n, g.k, g.vec_b, tid);
+            sa.store(lds, tid);
+            sb.store(lds + SA::HALVES, tid);
+        }
+        __syncthreads();
+        for (int64_t kt = 0; kt < ktiles; ++kt) {
+            const __bf16 *cur = lds + (kt & 1) * STAGE_HALVES;
+            __bf16 *nxt = lds + ((kt + 1) & 1) * STAGE_HALVES;
+            if (kt + 1 < ktiles) {
+                const int64_t k0 = (kt + 1) * SH::BK;
+                sa.load(g.A, g.lda, m0, k0, g.m, g.k, g.vec_a, tid);
+                sb.load(g.B, g.ldb, n0, k0, g.n, g.k, g.vec_b, tid);
+            }
+            // On the last block the store rewrites the idle buffer with the
+            // block already consumed; nothing reads it afterwards.  One body
+            // for every iteration keeps the accumulators in place.
+            body<true>(acc, cur, nxt, sa, sb, tid, wm, wn, half, l32);
+            __syncthreads();
+        }
+        epilogue<RM, RN>(g, acc, m0 + wm * SH::WM, n0 + wn * SH::WN, lane);
     }
 };
 

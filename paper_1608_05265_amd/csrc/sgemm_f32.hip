@@ -40,6 +40,7 @@ ConfigEntry make_f32(const char *name)
 void register_f32(std::vector<ConfigEntry> &out)
 {
     out.push_back(make_f32<Shape<256, 256, 16, 128, 64>, false>("fp32_256x256x16_w128x64"));
+    out.push_back(make_f32<Shape<256, 256, 32, 128, 64>, false>("fp32_256x256x32_w128x64"));
     out.push_back(make_f32<Shape<256, 128, 16, 128, 64>, true>("fp32_256x128x16_w128x64"));
     out.push_back(make_f32<Shape<128, 128, 16, 64, 64>, true>("fp32_128x128x16_w64x64"));
     out.push_back(make_f32<Shape<128, 64, 16, 64, 32>, true>("fp32_128x64x16_w64x32"));

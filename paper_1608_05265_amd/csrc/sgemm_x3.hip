@@ -15,6 +15,13 @@ using X3S = X3Tile<SH, TA, TB, false>;
 template <class SH, bool TA, bool TB>
 using X3D = X3Tile<SH, TA, TB, true>;
 
+// pipelined: split/store of the next block starts after 1/3 of the MFMAs
+template <class SH, bool TA, bool TB>
+using X3P13 = X3PTile<SH, TA, TB, 1, 3>;
+// the same with the order pinned by fences instead of group barriers
+template <class SH, bool TA, bool TB>
+using X3F13 = X3PTile<SH, TA, TB, 1, 3, true>;
+
 template <template <class, bool, bool> class T, class SH, bool BATCHED>
 ConfigEntry make_x3(const char *name)
 {
@@ -44,8 +51,11 @@ ConfigEntry make_x3(const char *name)
 
 void register_x3(std::vector<ConfigEntry> &out)
 {
-    out.push_back(make_x3<X3S, Shape<256, 256, 16, 128, 128>, false>("x3_256x256x16_w128x128"));
-    out.push_back(make_x3<X3D, Shape<256, 128, 16, 128, 64>, false>("x3d_256x128x16_w128x64"));
+    // 8 waves (two per SIMD): the other wave issues MFMAs while one splits
+    out.push_back(make_x3<X3F13, Shape<256, 256, 16, 128, 64>, false>("x3f_256x256x16_w128x64"));
+    out.push_back(make_x3<X3F13, Shape<256, 256, 16, 64, 128>, false>("x3f_256x256x16_w64x128"));
+    out.push_back(make_x3<X3F13, Shape<256, 256, 16, 128, 128>, false>("x3f_256x256x16_w128x128"));
+    out.push_back(make_x3<X3P13, Shape<128, 128, 16, 64, 64>, true>("x3p_128x128x16_w64x64"));
     out.push_back(make_x3<X3S, Shape<128, 128, 32, 64, 64>, true>("x3_128x128x32_w64x64"));
     out.push_back(make_x3<X3D, Shape<128, 128, 32, 64, 64>, true>("x3d_128x128x32_w64x64"));
     out.push_back(make_x3<X3S, Shape<64, 64, 32, 32, 32>, true>("x3_64x64x32_w32x32"));

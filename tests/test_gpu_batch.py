@@ -1,0 +1,111 @@
+"""The batched persistent form: many independent problems in one launch,
+every problem checked against the oracle, plus HIP-graph capture and replay."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1608_05265_amd import workloads as wl
+from tests import gpu_util as gu
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(problems):
+    import torch
+    dev = [gu.dev_problem(p) for p in problems]
+    c0 = [C.clone() for (_, _, C) in dev]
+    descs = [(p.transa, p.transb, p.m, p.n, p.k, p.alpha, A, p.lda, B, p.ldb, p.beta, C, p.ldc)
+             for p, (A, B, C) in zip(problems, dev)]
+    torch.cuda.synchronize()
+    return dev, c0, descs
+
+
+def _check_all(problems, dev, full, label):
+    for idx, (p, (_, _, C)) in enumerate(zip(problems, dev)):
+        out = C.cpu().numpy()[:p.C0.size]
+        if full:
+            gu.check_full(p, out, "%s problem %d" % (label, idx))
+        else:
+            gu.check_sampled(p, out, count=48, seed=idx, label="%s problem %d" % (label, idx))
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["fp32", "bf16x3"])
+def test_batch_small_every_batched_config(mode):
+    """64 problems of mixed shapes (including ragged, tiny and k = 0 ones),
+    run through every configuration that has a persistent variant."""
+    import torch
+    import paper_1608_05265_amd as mg
+    problems = wl.config5(count=60, seed_case=7, lo=1, hi=24, step=7)
+    problems.append(wl.make_problem("N", "N", 5, 3, 0, 1.0, 0.5, 11))      # k = 0
+    problems.append(wl.make_problem("T", "N", 9, 7, 4, 0.0, -1.0, 12))     # alpha = 0
+    problems.append(wl.make_problem("N", "T", 1, 1, 1, 2.0, 0.0, 13))      # 1x1x1
+    problems.append(wl.make_problem("T", "T", 33, 65, 17, 1.0, 1.0, 14, pad=3))
+    for cfg in mg.configs(mode):
+        dev, c0, descs = _setup(problems)
+        try:
+            plan = mg.Batch(descs, mode=mode, config_id=cfg["id"])
+        except mg.MisgemmError as e:
+            assert e.status == 1001  # no persistent variant for this config
+            continue
+        plan.launch()
+        torch.cuda.synchronize()
+        _check_all(problems, dev, True, cfg["name"])
+        plan.destroy()
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["fp32", "bf16x3"])
+def test_batch512_graph_replay(mode):
+    """The 512-problem batch: one eager launch checked against the oracle on
+    sampled entries of every problem, then captured into a HIP graph and
+    replayed several times with unrelated eager work in between; every
+    replay must equal the eager result bit for bit."""
+    import torch
+    import paper_1608_05265_amd as mg
+    problems = wl.config5()
+    dev, c0, descs = _setup(problems)
+    plan = mg.Batch(descs, mode=mode)
+    info = plan.info()
+    assert info["count"] == 512 and info["tiles"] > 0
+    plan.launch()
+    torch.cuda.synchronize()
+    _check_all(problems, dev, False, "batch512 mode %d" % mode)
+    eager = [C.clone() for (_, _, C) in dev]
+
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for (_, _, C), c in zip(dev, c0):
+            C.copy_(c)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        plan.launch()
+    scratch = torch.randn(1 << 20, device="cuda")
+    for rep in range(3):
+        for (_, _, C), c in zip(dev, c0):
+            C.copy_(c)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for idx, ((_, _, C), e) in enumerate(zip(dev, eager)):
+            assert torch.equal(C.view(torch.int32), e.view(torch.int32)), (rep, idx)
+        scratch.mul_(1.0001).add_(1.0)  # unrelated eager work between replays
+        torch.cuda.synchronize()
+    plan.destroy()
+
+
+def test_batch_plan_errors():
+    import paper_1608_05265_amd as mg
+    import torch
+    p = wl.make_problem("N", "N", 8, 8, 8, 1.0, 0.0, 1)
+    (A, B, C) = gu.dev_problem(p)
+    good = ("N", "N", 8, 8, 8, 1.0, A, 8, B, 8, 0.0, C, 8)
+    bad = ("N", "N", 8, 8, 8, 1.0, A, 4, B, 8, 0.0, C, 8)  # lda < m
+    with pytest.raises(mg.MisgemmError) as ei:
+        mg.Batch([good, good, bad], mode=0)
+    assert ei.value.status == -8 and ei.value.bad_index == 2
+    with pytest.raises(mg.MisgemmError) as ei:
+        mg.Batch([good], mode=0, config_id=0)  # 256x256 has no persistent variant
+    assert ei.value.status == 1001
+    torch.cuda.synchronize()
