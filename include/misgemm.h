@@ -86,15 +86,18 @@ int misgemm_sgemm(char transa, char transb, int64_t m, int64_t n, int64_t k,
 
 /*
  * misgemm_sgemm with an explicit kernel configuration (an index below
- * misgemm_num_configs(); the config's mode must equal `mode`).  Used by the
- * autotuner to time every candidate.  Errors as misgemm_sgemm, plus -15 for
- * an unknown config id or one of another mode.
+ * misgemm_num_configs(); the config's mode must equal `mode`) and tile
+ * order: group_m tile-rows of C are walked together so that concurrently
+ * running workgroups share panels of op(A) and op(B) in cache (0 = the
+ * default, 8).  Used by the autotuner to time every candidate.  Errors as
+ * misgemm_sgemm, plus -15 for an unknown config id or one of another mode
+ * and -16 for group_m outside [0, 4096].
  */
 int misgemm_sgemm_config(char transa, char transb, int64_t m, int64_t n, int64_t k,
                          float alpha, const float *A, int64_t lda,
                          const float *B, int64_t ldb,
                          float beta, float *C, int64_t ldc,
-                         int mode, int config_id, void *stream);
+                         int mode, int config_id, int group_m, void *stream);
 
 /* Description of one compiled kernel configuration. */
 typedef struct {
@@ -120,10 +123,17 @@ int misgemm_select_config(char transa, char transb, int64_t m, int64_t n, int64_
                           int mode);
 
 /*
- * Load the tuning table (JSON written by the autotuner) that maps
- * (mode, transposes, m, n, k) to a config name.  path == NULL clears it and
- * returns to the built-in heuristics.  Not thread-safe with concurrent
- * misgemm_sgemm calls.  Error: MISGEMM_E_TUNING_FILE.
+ * Load the tuning table written by the autotuner.  Text file: the header
+ * line "misgemm-tuning 1", then lines
+ *     <mode> <transa> <transb> <m> <n> <k> <config_name> [<group_m>]
+ * (a problem is served by the entry of its mode and transposes whose sizes
+ * are all within a factor 2 of its own, nearest in summed log-distance) and
+ *     batch <mode> <config_name>
+ * (the default configuration of batched plans); '#' starts a comment line.
+ * path == NULL clears the table and returns to the built-in heuristics.
+ * The table is replaced only when the whole file parses.  Not thread-safe
+ * with concurrent calls of the other entry points.
+ * Error: MISGEMM_E_TUNING_FILE.
  */
 int misgemm_load_tuning(const char *path);
 

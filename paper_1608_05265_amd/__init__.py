@@ -27,6 +27,9 @@ MODES = {"fp32": FP32, "bf16x3": BF16X3}
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libmisgemm.so")
+# Tuning table written by paper_1608_05265_amd.autotune on an MI355X; the
+# MISGEMM_TUNING environment variable names another file, or "none".
+TUNING_PATH = os.path.join(_HERE, "tuning_mi355x.txt")
 _lib = None
 
 
@@ -74,7 +77,7 @@ def _load():
     sig = [c, c, i64, i64, i64, f32, vp, i64, vp, i64, f32, vp, i64, i32]
     lib.misgemm_sgemm.argtypes = sig + [vp]
     lib.misgemm_sgemm.restype = i32
-    lib.misgemm_sgemm_config.argtypes = sig + [i32, vp]
+    lib.misgemm_sgemm_config.argtypes = sig + [i32, i32, vp]
     lib.misgemm_sgemm_config.restype = i32
     lib.misgemm_num_configs.argtypes = []
     lib.misgemm_num_configs.restype = i32
@@ -100,6 +103,9 @@ def _load():
     lib.misgemm_version.argtypes = []
     lib.misgemm_version.restype = ctypes.c_char_p
     _lib = lib
+    table = os.environ.get("MISGEMM_TUNING", TUNING_PATH)
+    if table != "none" and os.path.exists(table):
+        _check(lib.misgemm_load_tuning(table.encode()), "misgemm_load_tuning(%s)" % table)
     return lib
 
 
@@ -146,12 +152,12 @@ def sgemm(transa: str, transb: str, m: int, n: int, k: int, alpha: float, A, lda
 
 
 def sgemm_config(transa: str, transb: str, m: int, n: int, k: int, alpha: float, A, lda: int,
-                 B, ldb: int, beta: float, C, ldc: int, mode, config_id: int,
+                 B, ldb: int, beta: float, C, ldc: int, mode, config_id: int, group_m: int = 0,
                  stream=None) -> None:
-    """sgemm with an explicit kernel configuration id."""
+    """sgemm with an explicit kernel configuration id and tile order."""
     rc = _load().misgemm_sgemm_config(transa.encode(), transb.encode(), m, n, k, alpha, _ptr(A),
                                       lda, _ptr(B), ldb, beta, _ptr(C), ldc, _mode(mode),
-                                      config_id, _stream(stream))
+                                      config_id, group_m, _stream(stream))
     _check(rc, "misgemm_sgemm_config")
 
 

@@ -1,0 +1,168 @@
+"""Autotuner: pick the kernel configuration and tile order per problem shape.
+
+    python -m paper_1608_05265_amd.autotune --out paper_1608_05265_amd/tuning_mi355x.txt
+
+For every tuning key (mode, transposes, m, n, k) every compiled
+configuration of that mode is timed through the C-ABI
+(misgemm_sgemm_config, HIP events on the launching stream, median of
+several repetitions after warm-up), then the best one is timed again over a
+few tile orders (group_m); the winner goes into the tuning table that the
+library reads (include/misgemm.h, misgemm_load_tuning).  Batched plans are
+tuned the same way over the configurations with a persistent variant, on
+the batch workload.  The paper fixes its block sizes at compile time; here
+the search replaces that choice, per shape.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+GROUP_MS = [1, 4, 8, 16]
+
+
+def _time(fn, reps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    times = []
+    for _ in range(reps):
+        s = torch.cuda.Event(enable_timing=True)
+        e = torch.cuda.Event(enable_timing=True)
+        s.record(stream)
+        fn()
+        e.record(stream)
+        times.append((s, e))
+    torch.cuda.synchronize()
+    return statistics.median(s.elapsed_time(e) for s, e in times)
+
+
+def default_keys():
+    """Shapes of the workloads (square sweep, rank-k updates, the 256^3 case)
+    plus a grid of sizes between them, every transpose pair."""
+    keys = []
+    pairs = [("N", "N"), ("N", "T"), ("T", "N"), ("T", "T")]
+    for mode in (0, 1):
+        for ta, tb in pairs:
+            for s in (256, 512, 1024, 2048, 4096, 8192):
+                keys.append((mode, ta, tb, s, s, s))
+        for k in (128, 256, 512):
+            keys.append((mode, "N", "N", 16384, 16384, k))
+    return keys
+
+
+def tune_gemm(keys, reps=5, warmup=2, log=print):
+    import torch
+    import paper_1608_05265_amd as mg
+    dev = torch.device("cuda:0")
+    results = []
+    for (mode, ta, tb, m, n, k) in keys:
+        ar, ac = (k, m) if ta == "T" else (m, k)
+        br, bc = (n, k) if tb == "T" else (k, n)
+        A = torch.rand(ar * ac, device=dev) * 2 - 1
+        B = torch.rand(br * bc, device=dev) * 2 - 1
+        C = torch.rand(m * n, device=dev)
+        flops = 2.0 * m * n * k
+        small = flops < 2e10
+        r, w = (reps * 4, warmup * 2) if small else (reps, warmup)
+        timings = {}
+        for cfg in mg.configs(mode):
+            def fn(cid=cfg["id"]):
+                mg.sgemm_config(ta, tb, m, n, k, 1.0, A, ar, B, br, 0.5, C, m, mode, cid)
+            timings[cfg["name"]] = _time(fn, r, w)
+        best = min(timings, key=timings.get)
+        best_id = [c["id"] for c in mg.configs(mode) if c["name"] == best][0]
+        orders = {}
+        for gm in GROUP_MS:
+            def fn(gm=gm):
+                mg.sgemm_config(ta, tb, m, n, k, 1.0, A, ar, B, br, 0.5, C, m, mode, best_id, gm)
+            orders[gm] = _time(fn, r, w)
+        best_gm = min(orders, key=orders.get)
+        row = {"mode": mode, "ta": ta, "tb": tb, "m": m, "n": n, "k": k, "config": best,
+               "group_m": best_gm, "ms": orders[best_gm],
+               "tflops": flops / (orders[best_gm] * 1e-3) / 1e12,
+               "all_ms": timings, "group_m_ms": orders}
+        log("mode %d %s%s %6d %6d %6d -> %-26s gm=%-2d %8.3f ms %7.1f TF/s"
+            % (mode, ta, tb, m, n, k, best, best_gm, row["ms"], row["tflops"]))
+        results.append(row)
+        del A, B, C
+        torch.cuda.empty_cache()
+    return results
+
+
+def tune_batch(problems, reps=5, warmup=2, log=print):
+    import torch
+    import paper_1608_05265_amd as mg
+    dev = torch.device("cuda:0")
+    tensors = []
+    descs = []
+    for p in problems:
+        A = torch.from_numpy(p.A).to(dev)
+        B = torch.from_numpy(p.B).to(dev)
+        C = torch.from_numpy(p.C0).to(dev)
+        tensors.append((A, B, C))
+        descs.append((p.transa, p.transb, p.m, p.n, p.k, p.alpha, A, p.lda, B, p.ldb, p.beta, C,
+                      p.ldc))
+    flops = sum(p.flops() for p in problems)
+    out = {}
+    for mode in (0, 1):
+        timings = {}
+        for cfg in mg.configs(mode):
+            try:
+                plan = mg.Batch(descs, mode=mode, config_id=cfg["id"])
+            except mg.MisgemmError:
+                continue  # no persistent variant
+            timings[cfg["name"]] = _time(plan.launch, reps, warmup)
+            plan.destroy()
+        best = min(timings, key=timings.get)
+        out[mode] = {"config": best, "ms": timings[best],
+                     "tflops": flops / (timings[best] * 1e-3) / 1e12, "all_ms": timings}
+        log("batch mode %d -> %s %.3f ms %.1f TF/s" % (mode, best, timings[best],
+                                                       out[mode]["tflops"]))
+    return out
+
+
+def write_table(path, gemm_rows, batch):
+    with open(path, "w") as f:
+        f.write("misgemm-tuning 1\n")
+        f.write("# written by paper_1608_05265_amd.autotune on %s\n" % time.strftime("%Y-%m-%d"))
+        f.write("# mode transa transb m n k config group_m   (best TFLOP/s)\n")
+        for r in gemm_rows:
+            f.write("%d %s %s %d %d %d %s %d\n" % (r["mode"], r["ta"], r["tb"], r["m"], r["n"],
+                                                   r["k"], r["config"], r["group_m"]))
+            f.write("#   %.1f TFLOP/s\n" % r["tflops"])
+        for mode, b in sorted(batch.items()):
+            f.write("batch %d %s\n" % (mode, b["config"]))
+            f.write("#   %.1f TFLOP/s on the 512-problem batch\n" % b["tflops"])
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                   "tuning_mi355x.txt"))
+    ap.add_argument("--json", default=None, help="also dump every timing here")
+    ap.add_argument("--quick", action="store_true", help="fewer keys (smoke test of the tuner)")
+    args = ap.parse_args(argv)
+    os.environ["MISGEMM_TUNING"] = "none"  # tune from the built-in defaults
+    from paper_1608_05265_amd import workloads as wl
+    keys = default_keys()
+    if args.quick:
+        keys = [k for k in keys if k[3] <= 1024 and k[5] <= 1024][:6]
+    rows = tune_gemm(keys, log=lambda s: print(s, flush=True))
+    problems = wl.config5(count=64 if args.quick else 512)
+    batch = tune_batch(problems, log=lambda s: print(s, flush=True))
+    write_table(args.out, rows, batch)
+    if args.json:
+        with open(args.json, "w") as f:
+            json.dump({"gemm": rows, "batch": {str(k): v for k, v in batch.items()}}, f)
+    print("wrote", args.out)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -67,15 +67,16 @@ int trans_flag(char t)
 }
 
 // ---------------------------------------------------------------------------
-// Tuning table: lines "mode transa transb m n k config_name" after the
-// header line "misgemm-tuning 1".
+// Tuning table (format in include/misgemm.h, misgemm_load_tuning).
 // ---------------------------------------------------------------------------
 struct TuneEntry {
     int mode, ta, tb;
     int64_t m, n, k;
     int config;
+    int group_m;
 };
 std::vector<TuneEntry> g_tuning;
+int g_batch_config[2] = {-1, -1};  // per mode, from "batch" lines
 std::mutex g_tune_mutex;
 
 int find_config(const char *name)
@@ -86,7 +87,9 @@ int find_config(const char *name)
     return -1;
 }
 
-int tuned_config(int mode, int ta, int tb, int64_t m, int64_t n, int64_t k)
+// Nearest tuned entry (same mode and transposes, every size within a factor
+// 2, smallest summed log-distance); -1 when none.
+int tuned_config(int mode, int ta, int tb, int64_t m, int64_t n, int64_t k, int *group_m)
 {
     std::lock_guard<std::mutex> lock(g_tune_mutex);
     int best = -1;
@@ -96,9 +99,9 @@ int tuned_config(int mode, int ta, int tb, int64_t m, int64_t n, int64_t k)
         const double dm = fabs(log2((double)m / (double)e.m));
         const double dn = fabs(log2((double)n / (double)e.n));
         const double dk = fabs(log2((double)k / (double)e.k));
-        if (dm > 1.0 || dn > 1.0 || dk > 1.0) continue;  // only within a factor 2
+        if (dm > 1.0 || dn > 1.0 || dk > 1.0) continue;
         const double d = dm + dn + dk;
-        if (d < best_d) { best_d = d; best = e.config; }
+        if (d < best_d) { best_d = d; best = e.config; *group_m = e.group_m; }
     }
     return best;
 }
@@ -124,9 +127,11 @@ int heuristic_config(int mode, int64_t m, int64_t n, int64_t k, int cus)
     return best >= 0 ? best : smallest;
 }
 
-int select_config(int mode, int ta, int tb, int64_t m, int64_t n, int64_t k, int cus)
+int select_config(int mode, int ta, int tb, int64_t m, int64_t n, int64_t k, int cus,
+                  int *group_m)
 {
-    const int c = tuned_config(mode, ta, tb, m, n, k);
+    *group_m = GROUP_M_DEFAULT;
+    const int c = tuned_config(mode, ta, tb, m, n, k, group_m);
     if (c >= 0) return c;
     return heuristic_config(mode, m, n, k, cus);
 }
@@ -175,7 +180,7 @@ GemmArgs make_args(int64_t m, int64_t n, int64_t k, float alpha, const float *A,
 
 int run_sgemm(char transa, char transb, int64_t m, int64_t n, int64_t k, float alpha,
               const float *A, int64_t lda, const float *B, int64_t ldb, float beta, float *C,
-              int64_t ldc, int mode, int config_id, void *stream)
+              int64_t ldc, int mode, int config_id, int group_m, void *stream)
 {
     int rc = validate(transa, transb, m, n, k, alpha, A, lda, B, ldb, C, ldc, mode);
     if (rc != 0) return rc;
@@ -191,13 +196,15 @@ int run_sgemm(char transa, char transb, int64_t m, int64_t n, int64_t k, float a
     hipStream_t s = (hipStream_t)stream;
     if (alpha == 0.0f || k == 0) return (int)launch_scale(beta, C, m, n, ldc, s);
     const int ta = trans_flag(transa), tb = trans_flag(transb);
-    const int cfg = config_id >= 0 ? config_id : select_config(mode, ta, tb, m, n, k, dev->cus);
+    int gm = group_m > 0 ? group_m : GROUP_M_DEFAULT;
+    int cfg = config_id;
+    if (cfg < 0) cfg = select_config(mode, ta, tb, m, n, k, dev->cus, &gm);
     if (cfg < 0) return MISGEMM_E_BAD_CONFIG;
     const misgemm_config_desc &d = table[cfg].desc;
     const int64_t tiles = ((m + d.bm - 1) / d.bm) * ((n + d.bn - 1) / d.bn);
     if (tiles > INT32_MAX) return MISGEMM_E_TOO_LARGE;
     const GemmArgs g = make_args(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
-    return (int)table[cfg].launch[ta][tb](g, s);
+    return (int)table[cfg].launch[ta][tb](g, gm, s);
 }
 
 }  // namespace
@@ -222,17 +229,19 @@ int misgemm_sgemm(char transa, char transb, int64_t m, int64_t n, int64_t k, flo
                   const float *A, int64_t lda, const float *B, int64_t ldb, float beta, float *C,
                   int64_t ldc, int mode, void *stream)
 {
-    return run_sgemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, mode, -1,
+    return run_sgemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, mode, -1, 0,
                      stream);
 }
 
 int misgemm_sgemm_config(char transa, char transb, int64_t m, int64_t n, int64_t k, float alpha,
                          const float *A, int64_t lda, const float *B, int64_t ldb, float beta,
-                         float *C, int64_t ldc, int mode, int config_id, void *stream)
+                         float *C, int64_t ldc, int mode, int config_id, int group_m,
+                         void *stream)
 {
     if (config_id < 0) return -15;
+    if (group_m < 0 || group_m > 4096) return -16;
     return run_sgemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, mode,
-                     config_id, stream);
+                     config_id, group_m, stream);
 }
 
 int misgemm_num_configs(void) { return (int)configs().size(); }
@@ -257,12 +266,14 @@ int misgemm_select_config(char transa, char transb, int64_t m, int64_t n, int64_
     DeviceInfo *dev = nullptr;
     int cus = 256;
     if (current_device(&dev) == 0) cus = dev->cus;
-    return select_config(mode, ta, tb, m, n, k, cus);
+    int gm = 0;
+    return select_config(mode, ta, tb, m, n, k, cus, &gm);
 }
 
 int misgemm_load_tuning(const char *path)
 {
     std::vector<TuneEntry> entries;
+    int batch_cfg[2] = {-1, -1};
     if (path != nullptr) {
         FILE *f = fopen(path, "r");
         if (!f) return MISGEMM_E_TUNING_FILE;
@@ -276,18 +287,34 @@ int misgemm_load_tuning(const char *path)
                 header = true;
                 continue;
             }
+            char name[64];
             int mode;
+            if (strncmp(line, "batch ", 6) == 0) {
+                if (sscanf(line + 6, "%d %63s", &mode, name) != 2 || mode < 0 || mode > 1) {
+                    rc = MISGEMM_E_TUNING_FILE;
+                    break;
+                }
+                const int id = find_config(name);
+                if (id < 0 || configs()[id].desc.mode != mode || !configs()[id].batch) {
+                    rc = MISGEMM_E_TUNING_FILE;
+                    break;
+                }
+                batch_cfg[mode] = id;
+                continue;
+            }
             char ta, tb;
             long long m, n, k;
-            char name[64];
-            if (sscanf(line, "%d %c %c %lld %lld %lld %63s", &mode, &ta, &tb, &m, &n, &k, name) != 7 ||
-                m <= 0 || n <= 0 || k <= 0 || trans_flag(ta) < 0 || trans_flag(tb) < 0) {
+            int gm = GROUP_M_DEFAULT;
+            const int got = sscanf(line, "%d %c %c %lld %lld %lld %63s %d", &mode, &ta, &tb, &m,
+                                   &n, &k, name, &gm);
+            if (got < 7 || m <= 0 || n <= 0 || k <= 0 || trans_flag(ta) < 0 ||
+                trans_flag(tb) < 0 || gm <= 0 || gm > 4096) {
                 rc = MISGEMM_E_TUNING_FILE;
                 break;
             }
             const int id = find_config(name);
             if (id < 0 || configs()[id].desc.mode != mode) { rc = MISGEMM_E_TUNING_FILE; break; }
-            entries.push_back({mode, trans_flag(ta), trans_flag(tb), m, n, k, id});
+            entries.push_back({mode, trans_flag(ta), trans_flag(tb), m, n, k, id, gm});
         }
         fclose(f);
         if (rc == 0 && !header) rc = MISGEMM_E_TUNING_FILE;
@@ -295,6 +322,8 @@ int misgemm_load_tuning(const char *path)
     }
     std::lock_guard<std::mutex> lock(g_tune_mutex);
     g_tuning.swap(entries);
+    g_batch_config[0] = batch_cfg[0];
+    g_batch_config[1] = batch_cfg[1];
     return 0;
 }
 
@@ -321,6 +350,10 @@ int misgemm_batch_plan(const misgemm_problem *problems, int64_t count, int mode,
         if (cfg >= (int)table.size() || table[cfg].desc.mode != mode || !table[cfg].batch)
             return MISGEMM_E_BAD_CONFIG;
     } else {
+        {
+            std::lock_guard<std::mutex> lock(g_tune_mutex);
+            cfg = g_batch_config[mode];
+        }
         int64_t smallest = INT64_MAX;
         for (size_t i = 0; i < table.size(); ++i) {
             const misgemm_config_desc &d = table[i].desc;

@@ -26,7 +26,7 @@ struct TileDev {
     int32_t pad;
 };
 
-typedef hipError_t (*launch_fn)(const GemmArgs &g, hipStream_t s);
+typedef hipError_t (*launch_fn)(const GemmArgs &g, int group_m, hipStream_t s);
 typedef hipError_t (*batch_launch_fn)(const ProbDev *probs, const TileDev *tiles, int64_t ntiles,
                                       int grid, hipStream_t s);
 typedef int (*occupancy_fn)();
@@ -38,25 +38,26 @@ struct ConfigEntry {
     occupancy_fn batch_occupancy;
 };
 
-constexpr int GROUP_M = 8;
+// Default number of tile-rows walked together (see tile_coords).
+constexpr int GROUP_M_DEFAULT = 8;
 
 template <class TILE, class SH>
 __global__ __launch_bounds__(SH::NT, 1) void sgemm_kernel(GemmArgs g, int64_t tiles_m,
-                                                          int64_t tiles_n)
+                                                          int64_t tiles_n, int group_m)
 {
     __shared__ __attribute__((aligned(16))) char smem[TILE::LDS_BYTES];
     const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
     int64_t tm, tn;
-    tile_coords(t, tiles_m, tiles_n, GROUP_M, tm, tn);
+    tile_coords(t, tiles_m, tiles_n, group_m, tm, tn);
     TILE::run(g, tm * SH::BM, tn * SH::BN, smem);
 }
 
 template <class TILE, class SH>
-hipError_t launch_tile_kernel(const GemmArgs &g, hipStream_t s)
+hipError_t launch_tile_kernel(const GemmArgs &g, int group_m, hipStream_t s)
 {
     const int64_t tm = (g.m + SH::BM - 1) / SH::BM, tn = (g.n + SH::BN - 1) / SH::BN;
     hipLaunchKernelGGL((sgemm_kernel<TILE, SH>), dim3((unsigned)(tm * tn)), dim3(SH::NT), 0, s,
-                       g, tm, tn);
+                       g, tm, tn, group_m);
     return hipGetLastError();
 }
 

@@ -1,0 +1,123 @@
+"""The C-ABI library on the CPU: it loads, exports every entry point the
+header declares, validates arguments before touching a device, and parses
+tuning tables."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "misgemm.h")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(misgemm_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def mg():
+    import paper_1608_05265_amd as mg
+    if not os.path.exists(mg.library_path()):
+        from paper_1608_05265_amd import build
+        build.build()
+    return mg
+
+
+def test_every_declared_symbol_is_exported(mg):
+    names = header_functions()
+    assert len(names) >= 13
+    lib = ctypes.CDLL(mg.library_path())
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    out = subprocess.run(["nm", "-D", "--defined-only", mg.library_path()], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(line.split()[-1] for line in out.splitlines() if line.strip())
+    assert set(names) <= exported
+
+
+def test_configs_and_strings(mg):
+    n = mg.num_configs()
+    assert n >= 8
+    names = set()
+    for c in mg.configs():
+        assert c["mode"] in (0, 1)
+        assert c["bm"] % 32 == 0 and c["bn"] % 32 == 0 and c["threads"] % 64 == 0
+        assert 0 < c["lds_bytes"] <= 160 * 1024
+        names.add(c["name"])
+    assert len(names) == n
+    assert mg.status_string(0) == "success"
+    assert "position 8" in mg.status_string(-8)
+    assert "tuning" in mg.status_string(1003)
+    assert "gfx950" in mg.version()
+
+
+@pytest.mark.parametrize("case,expected", [
+    (dict(transa="X"), -1), (dict(transb="q"), -2), (dict(m=-1), -3), (dict(n=-1), -4),
+    (dict(k=-1), -5), (dict(lda=3), -8), (dict(ldb=3), -10), (dict(ldc=3), -13),
+    (dict(mode=7), -14), (dict(A=None), -7), (dict(B=None), -9), (dict(C=None), -12),
+    (dict(transa="T", lda=4), -8), (dict(transb="T", ldb=4), -10),
+])
+def test_argument_errors_before_any_launch(mg, case, expected):
+    """Invalid arguments are rejected with the BLAS position code; no device
+    is needed for that (the check precedes every HIP call)."""
+    args = dict(transa="N", transb="N", m=8, n=6, k=5, alpha=1.0, A=0x1000, lda=8, B=0x2000,
+                ldb=5, beta=0.0, C=0x3000, ldc=8, mode=0)
+    args.update(case)
+    lib = mg._load()
+    rc = lib.misgemm_sgemm(args["transa"].encode(), args["transb"].encode(), args["m"], args["n"],
+                           args["k"], args["alpha"], args["A"], args["lda"], args["B"],
+                           args["ldb"], args["beta"], args["C"], args["ldc"], args["mode"], None)
+    assert rc == expected
+
+
+def test_quick_returns_need_no_device(mg):
+    lib = mg._load()
+    # m == 0, n == 0, and (alpha == 0 or k == 0) with beta == 1 return before any HIP call
+    assert lib.misgemm_sgemm(b"N", b"N", 0, 5, 5, 1.0, None, 1, None, 5, 0.0, None, 1, 0, None) == 0
+    assert lib.misgemm_sgemm(b"N", b"N", 5, 0, 5, 1.0, None, 5, None, 5, 0.0, None, 5, 0, None) == 0
+    assert lib.misgemm_sgemm(b"N", b"N", 5, 5, 5, 0.0, None, 5, None, 5, 1.0, 0x10, 5, 1, None) == 0
+    assert lib.misgemm_sgemm(b"T", b"T", 5, 5, 0, 2.0, None, 1, None, 5, 1.0, 0x10, 5, 0, None) == 0
+    assert lib.misgemm_sgemm_config(b"N", b"N", 5, 5, 5, 1.0, 0x10, 5, 0x10, 5, 0.0, 0x10, 5, 0,
+                                    999, 0, None) == -15
+    assert lib.misgemm_sgemm_config(b"N", b"N", 5, 5, 5, 1.0, 0x10, 5, 0x10, 5, 0.0, 0x10, 5, 0,
+                                    0, -1, None) == -16
+    assert lib.misgemm_bf16x3_split(None, 0, None, None) == 0
+    assert lib.misgemm_bf16x3_split(None, 3, None, None) == -1
+    assert lib.misgemm_batch_launch(None, None) == 1005
+
+
+def test_tuning_table_parsing(mg, tmp_path):
+    cfgs = mg.configs()
+    f32 = [c for c in cfgs if c["mode"] == 0]
+    x3 = [c for c in cfgs if c["mode"] == 1]
+    good = tmp_path / "good.txt"
+    good.write_text("misgemm-tuning 1\n# comment\n0 N T 4096 4096 4096 %s 4\n"
+                    "1 T N 1000 2000 300 %s\n" % (f32[-1]["name"], x3[-1]["name"]))
+    mg.load_tuning(str(good))
+    assert mg.select_config("N", "T", 4096, 4096, 4096, 0) == f32[-1]["id"]
+    assert mg.select_config("N", "T", 3000, 5000, 2500, 0) == f32[-1]["id"]   # within 2x
+    assert mg.select_config("t", "n", 1000, 2000, 300, 1) == x3[-1]["id"]
+    bad_cases = ["nonsense\n", "misgemm-tuning 1\n0 N N 1 1 1 no_such_config\n",
+                 "misgemm-tuning 1\n1 N N 64 64 64 %s\n" % f32[0]["name"],  # mode mismatch
+                 "misgemm-tuning 1\n0 Q N 64 64 64 %s\n" % f32[0]["name"],
+                 "misgemm-tuning 1\n0 N N 0 64 64 %s\n" % f32[0]["name"],
+                 "misgemm-tuning 1\nbatch 0 %s\n" % f32[0]["name"]]  # no persistent variant
+    for i, text in enumerate(bad_cases):
+        p = tmp_path / ("bad%d.txt" % i)
+        p.write_text(text)
+        with pytest.raises(mg.MisgemmError) as ei:
+            mg.load_tuning(str(p))
+        assert ei.value.status == 1003
+    # a failed load keeps the previous table
+    assert mg.select_config("N", "T", 4096, 4096, 4096, 0) == f32[-1]["id"]
+    with pytest.raises(mg.MisgemmError):
+        mg.load_tuning(str(tmp_path / "missing.txt"))
+    mg.load_tuning(None)
+    assert mg.select_config("N", "T", 4096, 4096, 4096, 0) != -1
+    # restore the packaged table, if any, for later tests
+    if os.path.exists(mg.TUNING_PATH):
+        mg.load_tuning(mg.TUNING_PATH)
