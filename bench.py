@@ -42,7 +42,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="square",
-                    choices=["square", "c1", "rankk", "wide", "batch"])
+                    choices=["square", "c1", "rankk", "wide", "batch", "dominant"],
+                    help="dominant: only the 8192^3 NN problem of the square sweep in both "
+                         "forms plus a 1 GiB device copy, for counter collection")
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle leg (used under the profiler)")
     ap.add_argument("--no-batch", action="store_true",
@@ -283,6 +285,55 @@ def batch_line(args, torch, mg):
     return line
 
 
+COPY_BYTES = 1 << 30
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sgemm_dominant8192_hbm_counters.txt")
+KERNEL_SOURCES = ["gemm_tile.hpp", "registry.hpp", "sgemm_f32.hip", "sgemm_x3.hip"]
+
+
+def kernel_sources_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1608_05265_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(form: str):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE runs, calibrated on a copy kernel),
+    or None when the kernel sources changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            for line in f:
+                parts = line.split()
+                if len(parts) == 4 and parts[0] == "traffic_bytes_per_launch" and \
+                        parts[1] == form:
+                    return float(parts[3]) if parts[2] == kernel_sources_hash() else None
+    except OSError:
+        return None
+    return None
+
+
+def dominant_only(args, torch, mg):
+    """The dominant problem alone, for rocprofv3 runs: `steps` calls of the
+    8192^3 NN sgemm in each form, then `steps` device-to-device copies of
+    COPY_BYTES (a plain copy kernel of known traffic, to calibrate the HBM
+    byte counters)."""
+    from paper_1608_05265_amd import workloads as wl
+    r = Resident(wl.config2(8192, "N", "N"), torch.device("cuda:0"))
+    for mode in (mg.FP32, mg.BF16X3):
+        for _ in range(args.steps):
+            r.call(mg, mode)
+    src = torch.empty(COPY_BYTES // 4, device="cuda:0")
+    src.fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(args.steps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"workload": "dominant", "steps": args.steps, "copy_bytes": COPY_BYTES}))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -296,6 +347,9 @@ def main():
     if args.workload == "batch":
         line = batch_line(args, torch, mg)
         print(json.dumps(line))
+        return
+    if args.workload == "dominant":
+        dominant_only(args, torch, mg)
         return
     problems, desc = make_problems(args.workload)
     res = [Resident(p, dev) for p in problems]
@@ -368,7 +422,11 @@ def main():
             "frac": round(f32["dominant_tflops"] / PEAK_FP32, 4),
             "avg_launch_ms": round(f32["dominant_avg_ms"], 4),
             "flops_per_launch": 2.0 * dp.m * dp.n * dp.k,
-            "traffic": None,
+            "traffic": measured_traffic("fp32") if (dp.m, dp.n, dp.k) == (8192, 8192, 8192)
+            else None,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0, "
+                            "copy-kernel calibrated)",
+            "algorithmic_bytes_per_launch": 4.0 * (dp.m * dp.k + dp.k * dp.n + 2 * dp.m * dp.n),
         },
         "per_problem": per_problem,
     }

@@ -1,0 +1,86 @@
+"""Summaries of rocprofv3 CSV output (kernel trace and counter collection).
+
+    python -m paper_1608_05265_amd.profsummary trace <dir-with-kernel_trace.csv>
+    python -m paper_1608_05265_amd.profsummary pmc <dir-with-counter_collection.csv>
+
+`trace` groups dispatches by kernel and grid size and prints calls, average,
+minimum and maximum duration in microseconds; `pmc` prints the per-dispatch
+average of every collected counter, also grouped by kernel and grid size.
+Kernel names are shortened to the template arguments that identify a tile
+configuration.
+"""
+from __future__ import annotations
+
+import collections
+import csv
+import glob
+import os
+import re
+import sys
+
+
+def short_name(name: str) -> str:
+    m = re.search(r"misgemm::(\w+)<misgemm::(\w+)<misgemm::Shape<([\d, ]+)>, ([^>]*)>", name)
+    if m:
+        shape = "x".join(v.strip() for v in m.group(3).split(","))
+        return "%s<%s %s %s>" % (m.group(1), m.group(2), shape, m.group(4).replace(" ", ""))
+    m = re.search(r"misgemm::(\w+)<misgemm::[^,]*?(\w+), misgemm::Shape<([\d, ]+)>", name)
+    if m:
+        shape = "x".join(v.strip() for v in m.group(3).split(","))
+        return "%s<%s %s>" % (m.group(1), m.group(2), shape)
+    m = re.search(r"misgemm::(\w+)", name)
+    if m:
+        return m.group(1)
+    return name[:60]
+
+
+def _find(d: str, suffix: str) -> str:
+    hits = sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
+    if not hits:
+        raise FileNotFoundError("no *%s under %s" % (suffix, d))
+    return hits[0]
+
+
+def trace(d: str):
+    rows = list(csv.DictReader(open(_find(d, "kernel_trace.csv"))))
+    groups = collections.OrderedDict()
+    for r in rows:
+        grid = "%sx%sx%s" % (r.get("Grid_Size_X", r.get("Grid_Size", "?")),
+                             r.get("Grid_Size_Y", "1"), r.get("Grid_Size_Z", "1"))
+        key = (short_name(r["Kernel_Name"]), grid)
+        dur = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1000.0
+        groups.setdefault(key, []).append(dur)
+    out = ["%-58s %-16s %6s %11s %11s %11s" % ("kernel", "grid", "calls", "avg_us", "min_us",
+                                               "max_us")]
+    for (k, g), v in sorted(groups.items(), key=lambda kv: -sum(kv[1])):
+        out.append("%-58s %-16s %6d %11.2f %11.2f %11.2f" % (k, g, len(v), sum(v) / len(v),
+                                                             min(v), max(v)))
+    return "\n".join(out)
+
+
+def pmc(d: str):
+    rows = list(csv.DictReader(open(_find(d, "counter_collection.csv"))))
+    groups = collections.OrderedDict()
+    for r in rows:
+        key = (short_name(r["Kernel_Name"]), r.get("Grid_Size", "?"), r["Counter_Name"])
+        groups.setdefault(key, {})
+        groups[key].setdefault(r["Dispatch_Id"], 0.0)
+        groups[key][r["Dispatch_Id"]] += float(r["Counter_Value"])
+    out = ["%-58s %-10s %-14s %6s %16s" % ("kernel", "grid", "counter", "disp", "avg_per_disp")]
+    for (k, g, c), v in groups.items():
+        vals = list(v.values())
+        out.append("%-58s %-10s %-14s %6d %16.1f" % (k, g, c, len(vals), sum(vals) / len(vals)))
+    return "\n".join(out)
+
+
+def main(argv=None):
+    argv = sys.argv[1:] if argv is None else argv
+    if len(argv) != 2 or argv[0] not in ("trace", "pmc"):
+        print(__doc__)
+        return 2
+    print(trace(argv[1]) if argv[0] == "trace" else pmc(argv[1]))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
