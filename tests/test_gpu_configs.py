@@ -1,0 +1,212 @@
+"""GPU parity at the full workload sizes (sampled outputs checked one by one
+against the oracle), the split on its own, degenerate cases, argument errors,
+determinism and transposed-copy invariance."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1608_05265_amd import workloads as wl
+from tests import gpu_util as gu
+
+pytestmark = pytest.mark.gpu
+
+
+def _mg():
+    import paper_1608_05265_amd as mg
+    return mg
+
+
+def _free():
+    import torch
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("size", wl.SQUARE_SIZES)
+def test_square_sweep_full_size(size):
+    """The benchmark's square sweep, every transpose pair, both forms, in the
+    launch configuration the benchmark uses (the tuned default)."""
+    for ta, tb in wl.TRANS_PAIRS:
+        p = wl.config2(size, ta, tb)
+        tensors = gu.dev_problem(p)
+        for mode in (0, 1):
+            tensors[2].copy_(tensors[2].new_tensor(p.C0))
+            out = gu.run(p, mode, tensors=tensors)
+            label = "%s mode %d" % (p.label, mode)
+            if size <= 1024:
+                mx, mean, ratio = gu.check_full(p, out, label)
+            else:
+                mx, mean, ratio = gu.check_sampled(p, out, count=1024, seed=size, label=label)
+            print("%s max/bound %.3e" % (label, ratio))
+        del tensors
+        _free()
+
+
+@pytest.mark.parametrize("k", wl.RANKK_KS)
+def test_rankk_full_size(k):
+    p = wl.config3(k)
+    tensors = gu.dev_problem(p)
+    for mode in (0, 1):
+        tensors[2].copy_(tensors[2].new_tensor(p.C0))
+        out = gu.run(p, mode, tensors=tensors)
+        mx, mean, ratio = gu.check_sampled(p, out, count=1024, seed=k, label="%s mode %d" %
+                                           (p.label, mode))
+        print("%s mode %d max/bound %.3e" % (p.label, mode, ratio))
+    del tensors
+    _free()
+
+
+def test_wide_range_both_forms():
+    """Entries of both signs spread over 2^-8..2^8: both forms within the
+    bound on the same inputs, errors reported side by side."""
+    p = wl.config4()
+    tensors = gu.dev_problem(p)
+    stats = {}
+    for mode in (0, 1):
+        out = gu.run(p, mode, tensors=tensors)
+        stats[mode] = gu.check_sampled(p, out, count=2048, seed=4, label="wide mode %d" % mode)
+    print("wide 8192^3: fp32 max %.3e mean %.3e | bf16x3 max %.3e mean %.3e"
+          % (stats[0][0], stats[0][1], stats[1][0], stats[1][1]))
+    del tensors
+    _free()
+
+
+def test_split_matches_oracle_bit_exact():
+    """The GPU split (v_cvt_pk_bf16_f32 + FP32 residuals) equals the oracle's
+    split bit for bit: every significand at several binades, random bit
+    patterns over the whole domain, and edge values."""
+    import torch
+    mg = _mg()
+    mant = np.arange(1 << 23, dtype=np.uint32)
+    blocks = [((np.uint32(e) << 23) | mant) for e in (1, 17, 126, 127, 128, 200, 253)]
+    rng = np.random.default_rng(5)
+    rnd = rng.integers(0, 1 << 32, size=1 << 22, dtype=np.uint64).astype(np.uint32)
+    edge = np.array([0x7F7F7FFF, 0x0C800000, 0x3F808000, 0x3F818000, 0x00000000, 0x80000000],
+                    dtype=np.uint32)
+    bits = np.concatenate(blocks + [rnd, edge])
+    bits = np.concatenate([bits, bits | np.uint32(0x80000000)])
+    x = bits.view(np.float32)
+    ax = np.abs(x)
+    keep = np.isfinite(x) & ((ax >= 2.0 ** -110) | (ax == 0)) & (ax < np.float32(3.3e38))
+    x = np.ascontiguousarray(x[keep])
+    xd = torch.from_numpy(x).cuda()
+    parts = torch.empty(3 * x.size, dtype=torch.int16, device="cuda")
+    mg.bf16x3_split(xd, x.size, parts)
+    torch.cuda.synchronize()
+    got = parts.cpu().numpy().view(np.uint16).reshape(-1, 3)
+    ref = oracle.bf16x3_split(x)
+    bad = np.nonzero(np.any(got != ref, axis=1))[0]
+    assert bad.size == 0, "first mismatch at x=%r: gpu %s oracle %s" % (
+        x[bad[0]], got[bad[0]], ref[bad[0]])
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["fp32", "bf16x3"])
+def test_degenerate_cases(mode):
+    import torch
+    mg = _mg()
+    m, n, k = 37, 29, 23
+    p = wl.make_problem("N", "N", m, n, k, 1.0, 0.5, 3, pad=2)
+    A, B, C = gu.dev_problem(p)
+    nanA = torch.full_like(A, float("nan"))
+    nanB = torch.full_like(B, float("nan"))
+    # alpha = 0: A and B are not read
+    mg.sgemm("N", "N", m, n, k, 0.0, nanA, p.lda, nanB, p.ldb, -2.0, C, p.ldc, mode=mode)
+    out = C.cpu().numpy()
+    c0 = gu.c_dense(p, p.C0).astype(np.float64)
+    assert np.array_equal(gu.c_dense(p, out), (-2.0 * c0).astype(np.float32))
+    assert gu.padding_untouched(p, out)
+    # alpha = 0, beta = 1: quick return, C bit-identical
+    C.copy_(C.new_tensor(p.C0))
+    mg.sgemm("N", "N", m, n, k, 0.0, nanA, p.lda, nanB, p.ldb, 1.0, C, p.ldc, mode=mode)
+    assert np.array_equal(C.cpu().numpy().view(np.uint32), p.C0.view(np.uint32))
+    # k = 0, beta = 0: C = 0 even over NaN
+    C.fill_(float("nan"))
+    mg.sgemm("N", "N", m, n, 0, 1.0, A, p.lda, B, 1, 0.0, C, p.ldc, mode=mode)
+    out = C.cpu().numpy()
+    assert np.all(gu.c_dense(p, out) == 0)
+    # beta = 0 with NaN in C: C = alpha * A * B, no NaN
+    C.fill_(float("nan"))
+    mg.sgemm("N", "N", m, n, k, 1.0, A, p.lda, B, p.ldb, 0.0, C, p.ldc, mode=mode)
+    out = C.cpu().numpy()
+    cref, den = oracle.sgemm_f64("N", "N", m, n, k, 1.0, p.A, p.lda, p.B, p.ldb, 0.0, None,
+                                 p.ldc)
+    ok, mx, _, _ = oracle.check(gu.c_dense(p, out), cref, den, k)
+    assert ok
+    # m = 0 / n = 0: nothing touched
+    C.copy_(C.new_tensor(p.C0))
+    mg.sgemm("N", "N", 0, n, k, 1.0, A, 1, B, p.ldb, 0.0, C, 1, mode=mode)
+    mg.sgemm("N", "N", m, 0, k, 1.0, A, p.lda, B, p.ldb, 0.0, C, p.ldc, mode=mode)
+    torch.cuda.synchronize()
+    assert np.array_equal(C.cpu().numpy().view(np.uint32), p.C0.view(np.uint32))
+
+
+def test_argument_errors_leave_c_untouched():
+    import torch
+    mg = _mg()
+    p = wl.make_problem("N", "N", 16, 16, 16, 1.0, 0.0, 4)
+    A, B, C = gu.dev_problem(p)
+    before = C.clone()
+    for kwargs, code in ((dict(lda=8), -8), (dict(ldb=8), -10), (dict(ldc=8), -13),
+                         (dict(transa="Z"), -1), (dict(mode=5), -14)):
+        args = dict(transa="N", transb="N", lda=16, ldb=16, ldc=16, mode=0)
+        args.update(kwargs)
+        with pytest.raises(mg.MisgemmError) as ei:
+            mg.sgemm(args["transa"], args["transb"], 16, 16, 16, 1.0, A, args["lda"], B,
+                     args["ldb"], 0.0, C, args["ldc"], mode=args["mode"])
+        assert ei.value.status == code
+    torch.cuda.synchronize()
+    assert torch.equal(C.view(torch.int32), before.view(torch.int32))
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["fp32", "bf16x3"])
+def test_run_to_run_bitwise_determinism(mode):
+    """Same inputs, same configuration, same bits (also guards against LDS
+    races, which would show up as nondeterminism)."""
+    mg = _mg()
+    for cfg in mg.configs(mode):
+        p = wl.make_problem("T", "N", 3 * cfg["bm"] + 5, 2 * cfg["bn"] + 3, 257, 1.0, 0.0,
+                            70 + cfg["id"])
+        tensors = gu.dev_problem(p)
+        first = gu.run(p, mode, config_id=cfg["id"], tensors=tensors).copy()
+        for _ in range(2):
+            again = gu.run(p, mode, config_id=cfg["id"], tensors=tensors)
+            assert np.array_equal(first.view(np.uint32), again.view(np.uint32)), cfg["name"]
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["fp32", "bf16x3"])
+def test_transposed_copy_gives_same_bits(mode):
+    """Staging canonicalizes the operands: 'T' on an explicitly transposed
+    copy equals 'N' on the original bit for bit, for every configuration."""
+    import torch
+    mg = _mg()
+    for cfg in mg.configs(mode):
+        m, n, k = cfg["bm"] + 9, cfg["bn"] + 17, 3 * cfg["bk"] + 1
+        p = wl.make_problem("N", "N", m, n, k, 1.0, 0.0, 90 + cfg["id"])
+        a = p.A.reshape(k, m).T  # m x k
+        b = p.B.reshape(n, k).T  # k x n
+        At = np.ascontiguousarray(a).reshape(-1)  # column-major storage of a^T (k x m)
+        Bt = np.ascontiguousarray(b).reshape(-1)  # column-major storage of b^T (n x k)
+        outs = []
+        for (ta, tb, Ah, lda, Bh, ldb) in (("N", "N", p.A, m, p.B, k), ("T", "N", At, k, p.B, k),
+                                           ("N", "T", p.A, m, Bt, n), ("T", "T", At, k, Bt, n)):
+            A = torch.from_numpy(Ah).cuda()
+            B = torch.from_numpy(Bh).cuda()
+            C = torch.zeros(m * n, device="cuda")
+            mg.sgemm_config(ta, tb, m, n, k, 1.0, A, lda, B, ldb, 0.0, C, m, mode, cfg["id"])
+            torch.cuda.synchronize()
+            outs.append(C.cpu().numpy())
+        for o in outs[1:]:
+            assert np.array_equal(o.view(np.uint32), outs[0].view(np.uint32)), cfg["name"]
+
+
+def test_non_default_stream():
+    import torch
+    mg = _mg()
+    p = wl.make_problem("N", "T", 300, 200, 100, 1.0, 0.0, 8)
+    A, B, C = gu.dev_problem(p)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        mg.sgemm("N", "T", p.m, p.n, p.k, 1.0, A, p.lda, B, p.ldb, 0.0, C, p.ldc, stream=s)
+    s.synchronize()
+    gu.check_full(p, C.cpu().numpy(), "side stream")
