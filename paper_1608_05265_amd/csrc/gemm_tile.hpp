@@ -87,6 +87,13 @@ struct StageF32 {
         else    { r = (c % (R / 4)) * 4;   kk = c / (R / 4); }
     }
 
+    static constexpr bool NEEDS_VEC = true;  // the fast path uses 16-byte loads
+
+    // FAST: the caller guarantees the whole R x BK slice is in range and
+    // 16-byte aligned (an interior tile): unmasked loads, no branches, so the
+    // wait counters see straight-line code.  Otherwise every element is
+    // masked (zero fill outside the matrix).
+    template <bool FAST>
     __device__ __forceinline__ void load(const float *X, int64_t ld, int64_t r0, int64_t k0,
                                          int64_t rows, int64_t kdim, bool vec, int tid)
     {
@@ -97,7 +104,9 @@ struct StageF32 {
             int r, kk;
             chunk(c, r, kk);
             const int64_t gr = r0 + r, gk = k0 + kk;
-            if (KC) {
+            if (FAST) {
+                v[s] = *reinterpret_cast<const floatx4 *>(KC ? X + gk + gr * ld : X + gr + gk * ld);
+            } else if (KC) {
                 v[s] = load4(X + gk + gr * ld, vec, gr < rows, kdim - gk, 1);
             } else {
                 // four consecutive rows at one k: rows are the contiguous direction
@@ -160,20 +169,23 @@ struct StageX3 {
         kk = (c / R) * KS;
     }
 
+    static constexpr bool NEEDS_VEC = KC;  // only the K-contiguous side uses 16-byte loads
+
+    // FAST: the caller guarantees an interior, aligned slice (unmasked loads,
+    // straight-line code); otherwise every element is masked.
+    template <bool FAST>
     __device__ __forceinline__ void load(const float *X, int64_t ld, int64_t r0, int64_t k0,
                                          int64_t rows, int64_t kdim, bool vec, int tid)
     {
-        // Interior tiles (uniform across the workgroup) load without masks;
-        // edge tiles mask every element.
-        const bool interior = r0 + R <= rows && k0 + BK <= kdim && (vec || !KC);
-        if (interior) {
+        (void)vec;
 #pragma unroll
-            for (int s = 0; s < S; ++s) {
-                const int c = tid + s * NT;
-                if (!UNITS_FULL && c >= CH) break;
-                int r, kk;
-                chunk(c, r, kk);
-                const int64_t gr = r0 + r, gk = k0 + kk;
+        for (int s = 0; s < S; ++s) {
+            const int c = tid + s * NT;
+            if (!UNITS_FULL && c >= CH) break;
+            int r, kk;
+            chunk(c, r, kk);
+            const int64_t gr = r0 + r, gk = k0 + kk;
+            if (FAST) {
                 if (KC) {
                     const float *p = X + gk + gr * ld;
                     const floatx4 x0 = *reinterpret_cast<const floatx4 *>(p);
@@ -185,25 +197,18 @@ struct StageX3 {
 #pragma unroll
                     for (int e = 0; e < KS; ++e) v[s][e] = p[e * ld];
                 }
-            }
-            return;
-        }
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const int c = tid + s * NT;
-            if (!UNITS_FULL && c >= CH) break;
-            int r, kk;
-            chunk(c, r, kk);
-            const int64_t gr = r0 + r, gk = k0 + kk;
-            const bool in_r = gr < rows;
-            if (KC) {
-                const float *p = X + gk + gr * ld;
-#pragma unroll
-                for (int e = 0; e < KS; ++e) v[s][e] = (in_r && gk + e < kdim) ? p[e] : 0.0f;
             } else {
-                const float *p = X + gr + gk * ld;
+                const bool in_r = gr < rows;
+                if (KC) {
+                    const float *p = X + gk + gr * ld;
 #pragma unroll
-                for (int e = 0; e < KS; ++e) v[s][e] = (in_r && gk + e < kdim) ? p[e * ld] : 0.0f;
+                    for (int e = 0; e < KS; ++e) v[s][e] = (in_r && gk + e < kdim) ? p[e] : 0.0f;
+                } else {
+                    const float *p = X + gr + gk * ld;
+#pragma unroll
+                    for (int e = 0; e < KS; ++e)
+                        v[s][e] = (in_r && gk + e < kdim) ? p[e * ld] : 0.0f;
+                }
             }
         }
     }
@@ -306,8 +311,20 @@ struct F32Tile {
     static constexpr int LDS_BYTES = 2 * STAGE_FLOATS * 4;
     static constexpr int NT = SH::NT;
 
+    // Interior tiles whose K range is a whole number of blocks take the
+    // unmasked load path; every other tile masks its loads.
     __device__ __forceinline__ static void run(const GemmArgs &g, int64_t m0, int64_t n0,
                                                char *smem)
+    {
+        const bool fast = m0 + SH::BM <= g.m && n0 + SH::BN <= g.n && g.k % SH::BK == 0 &&
+                          (g.vec_a || !SA::NEEDS_VEC) && (g.vec_b || !SB::NEEDS_VEC);
+        if (fast) run_impl<true>(g, m0, n0, smem);
+        else run_impl<false>(g, m0, n0, smem);
+    }
+
+    template <bool FAST>
+    __device__ __forceinline__ static void run_impl(const GemmArgs &g, int64_t m0, int64_t n0,
+                                                    char *smem)
     {
         float *lds = reinterpret_cast<float *>(smem);
         const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -326,8 +343,8 @@ struct F32Tile {
         SA sa;
         SB sb;
         if (ktiles > 0) {
-            sa.load(g.A, g.lda, m0, 0, g.m, g.k, g.vec_a, tid);
-            sb.load(g.B, g.ldb, n0, 0, g.n, g.k, g.vec_b, tid);
+            sa.template load<FAST>(g.A, g.lda, m0, 0, g.m, g.k, g.vec_a, tid);
+            sb.template load<FAST>(g.B, g.ldb, n0, 0, g.n, g.k, g.vec_b, tid);
             sa.store(lds, tid);
             sb.store(lds + SA::FLOATS, tid);
         }
@@ -338,8 +355,8 @@ struct F32Tile {
             const bool more = kt + 1 < ktiles;
             if (more) {
                 const int64_t k0 = (kt + 1) * SH::BK;
-                sa.load(g.A, g.lda, m0, k0, g.m, g.k, g.vec_a, tid);
-                sb.load(g.B, g.ldb, n0, k0, g.n, g.k, g.vec_b, tid);
+                sa.template load<FAST>(g.A, g.lda, m0, k0, g.m, g.k, g.vec_a, tid);
+                sb.template load<FAST>(g.B, g.ldb, n0, k0, g.n, g.k, g.vec_b, tid);
             }
             const float *As = cur + wm * SH::WM + l32;
             const float *Bs = cur + SA::FLOATS + wn * SH::WN + l32;
@@ -368,6 +385,120 @@ struct F32Tile {
     }
 };
 
+// ---------------------------------------------------------------------------
+// Software-pipelined FP32 tile.  The operand fragments of K step s+1 are read
+// from LDS before the MFMAs of step s are issued (so a LDS round trip never
+// stalls the matrix core), and the LDS store of the next K block, whose
+// global loads were issued at the top of the block, sits between the MFMAs
+// of step STORE_STEP instead of after the last one.  The order is pinned
+// with sched_barrier.
+// ---------------------------------------------------------------------------
+template <class SH, bool TA, bool TB>
+struct F32PTile {
+    using SA = StageF32<SH::BM, SH::BK, SH::NT, TA>;
+    using SB = StageF32<SH::BN, SH::BK, SH::NT, !TB>;
+    static constexpr int STAGE_FLOATS = SA::FLOATS + SB::FLOATS;
+    static constexpr int LDS_BYTES = 2 * STAGE_FLOATS * 4;
+    static constexpr int NT = SH::NT;
+    static constexpr int RM = SH::RM, RN = SH::RN;
+    static constexpr int NKS = SH::BK / 2;           // MFMA K steps per block
+    static constexpr int STORE_STEP = NKS * 3 / 4;   // step that carries the store
+
+    __device__ __forceinline__ static void read_frag(const float *As, const float *Bs, int ks,
+                                                     int half, float (&a)[RM], float (&b)[RN])
+    {
+        const int kr = 2 * ks + half;  // lanes 0-31: even k, 32-63: odd k
+#pragma unroll
+        for (int i = 0; i < RM; ++i) a[i] = As[kr * SA::LD + i * 32];
+#pragma unroll
+        for (int j = 0; j < RN; ++j) b[j] = Bs[kr * SB::LD + j * 32];
+    }
+
+    __device__ __forceinline__ static void body(floatx16 (&acc)[RM][RN], const float *cur,
+                                                float *nxt, const SA &sa, const SB &sb, int tid,
+                                                int wm, int wn, int half, int l32)
+    {
+        const float *As = cur + wm * SH::WM + l32;
+        const float *Bs = cur + SA::FLOATS + wn * SH::WN + l32;
+        float a[2][RM], b[2][RN];
+        read_frag(As, Bs, 0, half, a[0], b[0]);
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks) {
+            if (ks + 1 < NKS) {
+                read_frag(As, Bs, ks + 1, half, a[(ks + 1) & 1], b[(ks + 1) & 1]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+#pragma unroll
+            for (int i = 0; i < RM; ++i)
+#pragma unroll
+                for (int j = 0; j < RN; ++j) {
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[ks & 1][i], b[ks & 1][j],
+                                                                      acc[i][j], 0, 0, 0);
+                    if (ks == STORE_STEP && i == 0 && j == 0) {
+                        __builtin_amdgcn_sched_barrier(0);
+                        sa.store(nxt, tid);
+                        sb.store(nxt + SA::FLOATS, tid);
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                }
+        }
+    }
+
+    // Interior tiles whose K range is a whole number of blocks take the
+    // unmasked load path; every other tile masks its loads.
+    __device__ __forceinline__ static void run(const GemmArgs &g, int64_t m0, int64_t n0,
+                                               char *smem)
+    {
+        const bool fast = m0 + SH::BM <= g.m && n0 + SH::BN <= g.n && g.k % SH::BK == 0 &&
+                          (g.vec_a || !SA::NEEDS_VEC) && (g.vec_b || !SB::NEEDS_VEC);
+        if (fast) run_impl<true>(g, m0, n0, smem);
+        else run_impl<false>(g, m0, n0, smem);
+    }
+
+    template <bool FAST>
+    __device__ __forceinline__ static void run_impl(const GemmArgs &g, int64_t m0, int64_t n0,
+                                                    char *smem)
+    {
+        float *lds = reinterpret_cast<float *>(smem);
+        const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+        const int wm = wave % SH::NWM, wn = wave / SH::NWM;
+        const int half = lane >> 5, l32 = lane & 31;
+
+        floatx16 acc[RM][RN];
+#pragma unroll
+        for (int i = 0; i < RM; ++i)
+#pragma unroll
+            for (int j = 0; j < RN; ++j)
+#pragma unroll
+                for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
+
+        const int64_t ktiles = (g.k + SH::BK - 1) / SH::BK;
+        SA sa;
+        SB sb;
+        if (ktiles > 0) {
+            sa.template load<FAST>(g.A, g.lda, m0, 0, g.m, g.k, g.vec_a, tid);
+            sb.template load<FAST>(g.B, g.ldb, n0, 0, g.n, g.k, g.vec_b, tid);
+            sa.store(lds, tid);
+            sb.store(lds + SA::FLOATS, tid);
+        }
+        __syncthreads();
+        for (int64_t kt = 0; kt < ktiles; ++kt) {
+            const float *cur = lds + (kt & 1) * STAGE_FLOATS;
+            float *nxt = lds + ((kt + 1) & 1) * STAGE_FLOATS;
+            if (kt + 1 < ktiles) {
+                const int64_t k0 = (kt + 1) * SH::BK;
+                sa.template load<FAST>(g.A, g.lda, m0, k0, g.m, g.k, g.vec_a, tid);
+                sb.template load<FAST>(g.B, g.ldb, n0, k0, g.n, g.k, g.vec_b, tid);
+            }
+            // On the last block the store rewrites the idle buffer with data
+            // already consumed; nothing reads it afterwards.
+            body(acc, cur, nxt, sa, sb, tid, wm, wn, half, l32);
+            __syncthreads();
+        }
+        epilogue<RM, RN>(g, acc, m0 + wm * SH::WM, n0 + wn * SH::WN, lane);
+    }
+};
+
 template <class SH, bool TA, bool TB, bool ACC2>
 struct X3Tile {
     using SA = StageX3<SH::BM, SH::BK, SH::NT, TA>;
@@ -377,8 +508,20 @@ struct X3Tile {
     static constexpr int LDS_BYTES = 2 * STAGE_HALVES * 2;
     static constexpr int NT = SH::NT;
 
+    // Interior tiles whose K range is a whole number of blocks take the
+    // unmasked load path; every other tile masks its loads.
     __device__ __forceinline__ static void run(const GemmArgs &g, int64_t m0, int64_t n0,
                                                char *smem)
+    {
+        const bool fast = m0 + SH::BM <= g.m && n0 + SH::BN <= g.n && g.k % SH::BK == 0 &&
+                          (g.vec_a || !SA::NEEDS_VEC) && (g.vec_b || !SB::NEEDS_VEC);
+        if (fast) run_impl<true>(g, m0, n0, smem);
+        else run_impl<false>(g, m0, n0, smem);
+    }
+
+    template <bool FAST>
+    __device__ __forceinline__ static void run_impl(const GemmArgs &g, int64_t m0, int64_t n0,
+                                                    char *smem)
     {
         __bf16 *lds = reinterpret_cast<__bf16 *>(smem);
         const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -406,8 +549,8 @@ struct X3Tile {
         SA sa;
         SB sb;
         if (ktiles > 0) {
-            sa.load(g.A, g.lda, m0, 0, g.m, g.k, g.vec_a, tid);
-            sb.load(g.B, g.ldb, n0, 0, g.n, g.k, g.vec_b, tid);
+            sa.template load<FAST>(g.A, g.lda, m0, 0, g.m, g.k, g.vec_a, tid);
+            sb.template load<FAST>(g.B, g.ldb, n0, 0, g.n, g.k, g.vec_b, tid);
             sa.store(lds, tid);
             sb.store(lds + SA::HALVES, tid);
         }
@@ -418,8 +561,8 @@ struct X3Tile {
             const bool more = kt + 1 < ktiles;
             if (more) {
                 const int64_t k0 = (kt + 1) * SH::BK;
-                sa.load(g.A, g.lda, m0, k0, g.m, g.k, g.vec_a, tid);
-                sb.load(g.B, g.ldb, n0, k0, g.n, g.k, g.vec_b, tid);
+                sa.template load<FAST>(g.A, g.lda, m0, k0, g.m, g.k, g.vec_a, tid);
+                sb.template load<FAST>(g.B, g.ldb, n0, k0, g.n, g.k, g.vec_b, tid);
             }
             const __bf16 *As = cur + (wm * SH::WM + l32) * SA::LD + half * 8;
             const __bf16 *Bs = cur + SA::HALVES + (wn * SH::WN + l32) * SB::LD + half * 8;
@@ -622,8 +765,20 @@ struct X3PTile {
         }
     }
 
+    // Interior tiles whose K range is a whole number of blocks take the
+    // unmasked load path; every other tile masks its loads.
     __device__ __forceinline__ static void run(const GemmArgs &g, int64_t m0, int64_t n0,
                                                char *smem)
+    {
+        const bool fast = m0 + SH::BM <= g.m && n0 + SH::BN <= g.n && g.k % SH::BK == 0 &&
+                          (g.vec_a || !SA::NEEDS_VEC) && (g.vec_b || !SB::NEEDS_VEC);
+        if (fast) run_impl<true>(g, m0, n0, smem);
+        else run_impl<false>(g, m0, n0, smem);
+    }
+
+    template <bool FAST>
+    __device__ __forceinline__ static void run_impl(const GemmArgs &g, int64_t m0, int64_t n0,
+                                                    char *smem)
     {
         __bf16 *lds = reinterpret_cast<__bf16 *>(smem);
         const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -642,8 +797,8 @@ struct X3PTile {
         SA sa;
         SB sb;
         if (ktiles > 0) {
-            sa.load(g.A, g.lda, m0, 0, g.m, g.k, g.vec_a, tid);
-            sb.load(g.B, g.ldb, n0, 0, g.n, g.k, g.vec_b, tid);
+            sa.template load<FAST>(g.A, g.lda, m0, 0, g.m, g.k, g.vec_a, tid);
+            sb.template load<FAST>(g.B, g.ldb, n0, 0, g.n, g.k, g.vec_b, tid);
             sa.store(lds, tid);
             sb.store(lds + SA::HALVES, tid);
         }
@@ -653,8 +808,8 @@ struct X3PTile {
             __bf16 *nxt = lds + ((kt + 1) & 1) * STAGE_HALVES;
             if (kt + 1 < ktiles) {
                 const int64_t k0 = (kt + 1) * SH::BK;
-                sa.load(g.A, g.lda, m0, k0, g.m, g.k, g.vec_a, tid);
-                sb.load(g.B, g.ldb, n0, k0, g.n, g.k, g.vec_b, tid);
+                sa.template load<FAST>(g.A, g.lda, m0, k0, g.m, g.k, g.vec_a, tid);
+                sb.template load<FAST>(g.B, g.ldb, n0, k0, g.n, g.k, g.vec_b, tid);
             }
             // On the last block the store rewrites the idle buffer with the
             // block already consumed; nothing reads it afterwards.  One body

@@ -9,8 +9,10 @@ namespace {
 
 template <class SH, bool TA, bool TB>
 using F32 = F32Tile<SH, TA, TB>;
+template <class SH, bool TA, bool TB>
+using F32P = F32PTile<SH, TA, TB>;
 
-template <class SH, bool BATCHED>
+template <template <class, bool, bool> class T, class SH, bool BATCHED>
 ConfigEntry make_f32(const char *name)
 {
     ConfigEntry e;
@@ -22,15 +24,15 @@ ConfigEntry make_f32(const char *name)
     e.desc.wm = SH::WM;
     e.desc.wn = SH::WN;
     e.desc.threads = SH::NT;
-    e.desc.lds_bytes = F32<SH, false, false>::LDS_BYTES;
+    e.desc.lds_bytes = T<SH, false, false>::LDS_BYTES;
     strncpy(e.desc.name, name, sizeof(e.desc.name) - 1);
-    e.launch[0][0] = launch_tile_kernel<F32<SH, false, false>, SH>;
-    e.launch[0][1] = launch_tile_kernel<F32<SH, false, true>, SH>;
-    e.launch[1][0] = launch_tile_kernel<F32<SH, true, false>, SH>;
-    e.launch[1][1] = launch_tile_kernel<F32<SH, true, true>, SH>;
+    e.launch[0][0] = launch_tile_kernel<T<SH, false, false>, SH>;
+    e.launch[0][1] = launch_tile_kernel<T<SH, false, true>, SH>;
+    e.launch[1][0] = launch_tile_kernel<T<SH, true, false>, SH>;
+    e.launch[1][1] = launch_tile_kernel<T<SH, true, true>, SH>;
     if constexpr (BATCHED) {
-        e.batch = launch_batch_kernel<F32, SH>;
-        e.batch_occupancy = batch_occupancy<F32, SH>;
+        e.batch = launch_batch_kernel<T, SH>;
+        e.batch_occupancy = batch_occupancy<T, SH>;
     }
     return e;
 }
@@ -39,12 +41,14 @@ ConfigEntry make_f32(const char *name)
 
 void register_f32(std::vector<ConfigEntry> &out)
 {
-    out.push_back(make_f32<Shape<256, 256, 16, 128, 64>, false>("fp32_256x256x16_w128x64"));
-    out.push_back(make_f32<Shape<256, 256, 32, 128, 64>, false>("fp32_256x256x32_w128x64"));
-    out.push_back(make_f32<Shape<256, 128, 16, 128, 64>, true>("fp32_256x128x16_w128x64"));
-    out.push_back(make_f32<Shape<128, 128, 16, 64, 64>, true>("fp32_128x128x16_w64x64"));
-    out.push_back(make_f32<Shape<128, 64, 16, 64, 32>, true>("fp32_128x64x16_w64x32"));
-    out.push_back(make_f32<Shape<64, 64, 16, 32, 32>, true>("fp32_64x64x16_w32x32"));
+    out.push_back(make_f32<F32P, Shape<256, 256, 16, 128, 64>, false>("fp32p_256x256x16_w128x64"));
+    out.push_back(make_f32<F32P, Shape<256, 256, 32, 128, 64>, false>("fp32p_256x256x32_w128x64"));
+    out.push_back(make_f32<F32P, Shape<128, 128, 16, 64, 64>, true>("fp32p_128x128x16_w64x64"));
+    out.push_back(make_f32<F32P, Shape<128, 128, 32, 64, 64>, true>("fp32p_128x128x32_w64x64"));
+    out.push_back(make_f32<F32P, Shape<64, 64, 32, 32, 32>, true>("fp32p_64x64x32_w32x32"));
+    out.push_back(make_f32<F32, Shape<128, 128, 16, 64, 64>, true>("fp32_128x128x16_w64x64"));
+    out.push_back(make_f32<F32, Shape<128, 64, 16, 64, 32>, true>("fp32_128x64x16_w64x32"));
+    out.push_back(make_f32<F32, Shape<64, 64, 16, 32, 32>, true>("fp32_64x64x16_w32x32"));
 }
 
 }  // namespace misgemm
