@@ -99,6 +99,40 @@ int misgemm_sgemm_config(char transa, char transb, int64_t m, int64_t n, int64_t
                          float beta, float *C, int64_t ldc,
                          int mode, int config_id, int group_m, void *stream);
 
+/*
+ * Workspace for the packed bf16x3 path.  Packed configurations first split
+ * op(A) and op(B) into bf16 panels (the BLIS packing step: for each block of
+ * 16 k, each of the three parts, each row, 16 consecutive values), then run
+ * one tile kernel on the panels.  The panels take
+ * 6 * ceil(k/16)*16 * (roundup(m,256) + roundup(n,256)) bytes (plus 512).
+ *
+ * misgemm_workspace_size: bytes misgemm_sgemm_ws needs for the packed path
+ *   of this problem (0 for MISGEMM_FP32); negative = argument error as in
+ *   misgemm_sgemm.
+ * misgemm_sgemm_ws: misgemm_sgemm with a caller-owned device workspace
+ *   (16-byte aligned).  workspace == NULL: a packed configuration is never
+ *   chosen and nothing is allocated; otherwise workspace_bytes must cover
+ *   misgemm_workspace_size (-16 if not, -15 if misaligned) and the call
+ *   allocates nothing (capturable).  The workspace must not be reused by
+ *   another call before this one completes on `stream`.
+ * misgemm_sgemm itself, in MISGEMM_BF16X3 mode with a packed configuration
+ *   selected, uses a workspace the library owns per device: grown with
+ *   hipMalloc when a larger problem arrives (never while the stream is being
+ *   captured; then a non-packed configuration is used instead).  Buffers are
+ *   kept, including outgrown ones that earlier captured graphs may still
+ *   reference, until misgemm_release_workspace().
+ * misgemm_release_workspace: synchronizes the current device and frees the
+ *   library-owned workspaces of that device.
+ */
+int64_t misgemm_workspace_size(char transa, char transb, int64_t m, int64_t n, int64_t k,
+                               int mode);
+int misgemm_sgemm_ws(char transa, char transb, int64_t m, int64_t n, int64_t k,
+                     float alpha, const float *A, int64_t lda,
+                     const float *B, int64_t ldb,
+                     float beta, float *C, int64_t ldc,
+                     int mode, void *workspace, int64_t workspace_bytes, void *stream);
+int misgemm_release_workspace(void);
+
 /* Description of one compiled kernel configuration. */
 typedef struct {
     int mode;          /* misgemm_mode                                  */
@@ -106,7 +140,9 @@ typedef struct {
     int wm, wn;        /* per-wave tile of C                            */
     int threads;       /* threads per workgroup (64 per wave)           */
     int lds_bytes;     /* LDS used per workgroup                        */
-    char name[48];     /* e.g. "fp32_256x256x16_w128x64"               */
+    int packed;        /* 1: operands are first split into packed panels
+                          in a workspace (bf16x3 only), 0: split in LDS  */
+    char name[48];     /* e.g. "fp32p_256x256x16_w128x64"              */
 } misgemm_config_desc;
 
 /* Number of compiled configurations (ids 0 .. n-1). */

@@ -17,7 +17,8 @@ import ctypes
 import os
 from typing import List, Optional, Sequence
 
-__all__ = ["MisgemmError", "FP32", "BF16X3", "sgemm", "sgemm_config", "num_configs",
+__all__ = ["MisgemmError", "FP32", "BF16X3", "sgemm", "sgemm_config", "sgemm_ws",
+           "workspace_size", "release_workspace", "num_configs",
            "config_info", "configs", "select_config", "load_tuning", "Batch", "bf16x3_split",
            "status_string", "version", "library_path"]
 
@@ -43,7 +44,7 @@ class ConfigDesc(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("bm", ctypes.c_int), ("bn", ctypes.c_int),
                 ("bk", ctypes.c_int), ("wm", ctypes.c_int), ("wn", ctypes.c_int),
                 ("threads", ctypes.c_int), ("lds_bytes", ctypes.c_int),
-                ("name", ctypes.c_char * 48)]
+                ("packed", ctypes.c_int), ("name", ctypes.c_char * 48)]
 
 
 class Problem(ctypes.Structure):
@@ -79,6 +80,12 @@ def _load():
     lib.misgemm_sgemm.restype = i32
     lib.misgemm_sgemm_config.argtypes = sig + [i32, i32, vp]
     lib.misgemm_sgemm_config.restype = i32
+    lib.misgemm_sgemm_ws.argtypes = sig + [vp, i64, vp]
+    lib.misgemm_sgemm_ws.restype = i32
+    lib.misgemm_workspace_size.argtypes = [c, c, i64, i64, i64, i32]
+    lib.misgemm_workspace_size.restype = i64
+    lib.misgemm_release_workspace.argtypes = []
+    lib.misgemm_release_workspace.restype = i32
     lib.misgemm_num_configs.argtypes = []
     lib.misgemm_num_configs.restype = i32
     lib.misgemm_config_info.argtypes = [i32, ctypes.POINTER(ConfigDesc)]
@@ -161,6 +168,27 @@ def sgemm_config(transa: str, transb: str, m: int, n: int, k: int, alpha: float,
     _check(rc, "misgemm_sgemm_config")
 
 
+def sgemm_ws(transa: str, transb: str, m: int, n: int, k: int, alpha: float, A, lda: int, B,
+             ldb: int, beta: float, C, ldc: int, mode, workspace, workspace_bytes: int,
+             stream=None) -> None:
+    """sgemm with a caller-owned workspace (None: never use a packed config)."""
+    rc = _load().misgemm_sgemm_ws(transa.encode(), transb.encode(), m, n, k, alpha, _ptr(A), lda,
+                                  _ptr(B), ldb, beta, _ptr(C), ldc, _mode(mode), _ptr(workspace),
+                                  workspace_bytes, _stream(stream))
+    _check(rc, "misgemm_sgemm_ws")
+
+
+def workspace_size(transa: str, transb: str, m: int, n: int, k: int, mode) -> int:
+    rc = _load().misgemm_workspace_size(transa.encode(), transb.encode(), m, n, k, _mode(mode))
+    if rc < 0:
+        raise MisgemmError(int(rc), "misgemm_workspace_size")
+    return int(rc)
+
+
+def release_workspace() -> None:
+    _check(_load().misgemm_release_workspace(), "misgemm_release_workspace")
+
+
 def num_configs() -> int:
     return _load().misgemm_num_configs()
 
@@ -170,7 +198,7 @@ def config_info(config_id: int) -> dict:
     _check(_load().misgemm_config_info(config_id, ctypes.byref(d)), "misgemm_config_info")
     return {"id": config_id, "mode": d.mode, "bm": d.bm, "bn": d.bn, "bk": d.bk, "wm": d.wm,
             "wn": d.wn, "threads": d.threads, "lds_bytes": d.lds_bytes,
-            "name": d.name.decode()}
+            "packed": d.packed, "name": d.name.decode()}
 
 
 def configs(mode=None) -> List[dict]:

@@ -24,6 +24,7 @@ std::vector<ConfigEntry> &configs()
     std::call_once(once, [] {
         register_f32(table);
         register_x3(table);
+        register_x3k(table);
     });
     return table;
 }
@@ -107,33 +108,96 @@ int tuned_config(int mode, int ta, int tb, int64_t m, int64_t n, int64_t k, int 
 }
 
 // Built-in choice: the largest tile that still gives every CU at least one
-// tile; below that the smallest tile (fewest idle CUs).
-int heuristic_config(int mode, int64_t m, int64_t n, int64_t k, int cus)
+// tile (packed configurations first on equal area, when allowed); below that
+// the smallest tile (fewest idle CUs).
+int heuristic_config(int mode, int64_t m, int64_t n, int64_t k, int cus, bool allow_packed)
 {
     (void)k;
     const auto &t = configs();
     int best = -1;
-    int64_t best_area = -1;
+    int64_t best_key = -1;
     int smallest = -1;
     int64_t smallest_area = INT64_MAX;
     for (size_t i = 0; i < t.size(); ++i) {
         const misgemm_config_desc &d = t[i].desc;
-        if (d.mode != mode) continue;
+        if (d.mode != mode || (d.packed && !allow_packed)) continue;
         const int64_t area = (int64_t)d.bm * d.bn;
+        const int64_t key = 2 * area + (d.packed ? 1 : 0);
         const int64_t tiles = ((m + d.bm - 1) / d.bm) * ((n + d.bn - 1) / d.bn);
-        if (tiles >= cus && area > best_area) { best_area = area; best = (int)i; }
+        if (tiles >= cus && key > best_key) { best_key = key; best = (int)i; }
         if (area < smallest_area) { smallest_area = area; smallest = (int)i; }
     }
     return best >= 0 ? best : smallest;
 }
 
 int select_config(int mode, int ta, int tb, int64_t m, int64_t n, int64_t k, int cus,
-                  int *group_m)
+                  bool allow_packed, int *group_m)
 {
     *group_m = GROUP_M_DEFAULT;
     const int c = tuned_config(mode, ta, tb, m, n, k, group_m);
-    if (c >= 0) return c;
-    return heuristic_config(mode, m, n, k, cus);
+    if (c >= 0 && (allow_packed || !configs()[c].desc.packed)) return c;
+    *group_m = GROUP_M_DEFAULT;
+    return heuristic_config(mode, m, n, k, cus, allow_packed);
+}
+
+// ---------------------------------------------------------------------------
+// Workspace of the packed path.
+// ---------------------------------------------------------------------------
+int64_t packed_bytes(int64_t m, int64_t n, int64_t k)
+{
+    return 2 * (pack_halves(m, k) + pack_halves(n, k)) + 512;
+}
+
+struct DeviceWorkspace {
+    void *ptr = nullptr;
+    int64_t bytes = 0;
+    std::vector<void *> retired;  // outgrown buffers, kept for captured graphs
+};
+DeviceWorkspace g_ws[64];
+std::mutex g_ws_mutex;
+
+// Library-owned workspace of at least `bytes` on the current device, or
+// nullptr when it would have to grow while `s` is capturing or the
+// allocation fails.
+void *library_workspace(int64_t bytes, hipStream_t s)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    std::lock_guard<std::mutex> lock(g_ws_mutex);
+    DeviceWorkspace &w = g_ws[dev];
+    if (w.bytes >= bytes) return w.ptr;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone)
+        return nullptr;
+    const int64_t want = std::max<int64_t>(bytes, w.bytes + w.bytes / 2);
+    void *p = nullptr;
+    if (hipMalloc(&p, (size_t)want) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    if (w.ptr) w.retired.push_back(w.ptr);
+    w.ptr = p;
+    w.bytes = want;
+    return p;
+}
+
+hipError_t launch_packed_path(const ConfigEntry &cfg, int ta, int tb, const GemmArgs &g,
+                              void *ws, int group_m, hipStream_t s)
+{
+    __bf16 *ap = reinterpret_cast<__bf16 *>(((uintptr_t)ws + 255) & ~(uintptr_t)255);
+    __bf16 *bp = ap + pack_halves(g.m, g.k);
+    hipError_t e = launch_pack(g.A, g.lda, ta != 0, g.m, g.k, g.vec_a, ap, s);
+    if (e != hipSuccess) return e;
+    e = launch_pack(g.B, g.ldb, tb == 0, g.n, g.k, g.vec_b, bp, s);
+    if (e != hipSuccess) return e;
+    PackedArgs p;
+    p.g = g;
+    p.Ap = ap;
+    p.Bp = bp;
+    p.mp = pack_rows_pad(g.m);
+    p.np = pack_rows_pad(g.n);
+    p.kblocks = pack_kblocks(g.k);
+    return cfg.packed(p, group_m, s);
 }
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
@@ -178,9 +242,13 @@ GemmArgs make_args(int64_t m, int64_t n, int64_t k, float alpha, const float *A,
     return g;
 }
 
+// Workspace policy of one call.
+enum WsPolicy { WS_LIBRARY, WS_CALLER, WS_NONE };
+
 int run_sgemm(char transa, char transb, int64_t m, int64_t n, int64_t k, float alpha,
               const float *A, int64_t lda, const float *B, int64_t ldb, float beta, float *C,
-              int64_t ldc, int mode, int config_id, int group_m, void *stream)
+              int64_t ldc, int mode, int config_id, int group_m, void *stream,
+              WsPolicy policy = WS_LIBRARY, void *workspace = nullptr, int64_t ws_bytes = 0)
 {
     int rc = validate(transa, transb, m, n, k, alpha, A, lda, B, ldb, C, ldc, mode);
     if (rc != 0) return rc;
@@ -197,13 +265,29 @@ int run_sgemm(char transa, char transb, int64_t m, int64_t n, int64_t k, float a
     if (alpha == 0.0f || k == 0) return (int)launch_scale(beta, C, m, n, ldc, s);
     const int ta = trans_flag(transa), tb = trans_flag(transb);
     int gm = group_m > 0 ? group_m : GROUP_M_DEFAULT;
+    const bool packable = mode == MISGEMM_BF16X3 && policy != WS_NONE &&
+                          pack_kblocks(k) <= 65535;
     int cfg = config_id;
-    if (cfg < 0) cfg = select_config(mode, ta, tb, m, n, k, dev->cus, &gm);
+    if (cfg < 0) cfg = select_config(mode, ta, tb, m, n, k, dev->cus, packable, &gm);
     if (cfg < 0) return MISGEMM_E_BAD_CONFIG;
+    void *ws = nullptr;
+    if (table[cfg].desc.packed) {
+        if (pack_kblocks(k) > 65535) return MISGEMM_E_TOO_LARGE;
+        const int64_t need = packed_bytes(m, n, k);
+        if (policy == WS_CALLER) ws = workspace;
+        else if (policy == WS_LIBRARY) ws = library_workspace(need, s);
+        if (ws == nullptr) {
+            if (config_id >= 0 && policy == WS_LIBRARY && !packable) return MISGEMM_E_CAPTURING;
+            // no workspace (capturing, or none given): a non-packed config
+            cfg = heuristic_config(mode, m, n, k, dev->cus, false);
+            gm = group_m > 0 ? group_m : GROUP_M_DEFAULT;
+        }
+    }
     const misgemm_config_desc &d = table[cfg].desc;
     const int64_t tiles = ((m + d.bm - 1) / d.bm) * ((n + d.bn - 1) / d.bn);
     if (tiles > INT32_MAX) return MISGEMM_E_TOO_LARGE;
     const GemmArgs g = make_args(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+    if (d.packed) return (int)launch_packed_path(table[cfg], ta, tb, g, ws, gm, s);
     return (int)table[cfg].launch[ta][tb](g, gm, s);
 }
 
@@ -244,6 +328,52 @@ int misgemm_sgemm_config(char transa, char transb, int64_t m, int64_t n, int64_t
                      config_id, group_m, stream);
 }
 
+int64_t misgemm_workspace_size(char transa, char transb, int64_t m, int64_t n, int64_t k,
+                               int mode)
+{
+    if (trans_flag(transa) < 0) return -1;
+    if (trans_flag(transb) < 0) return -2;
+    if (m < 0) return -3;
+    if (n < 0) return -4;
+    if (k < 0) return -5;
+    if (mode != MISGEMM_FP32 && mode != MISGEMM_BF16X3) return -6;
+    if (mode == MISGEMM_FP32 || m == 0 || n == 0 || k == 0) return 0;
+    return packed_bytes(m, n, k);
+}
+
+int misgemm_sgemm_ws(char transa, char transb, int64_t m, int64_t n, int64_t k, float alpha,
+                     const float *A, int64_t lda, const float *B, int64_t ldb, float beta,
+                     float *C, int64_t ldc, int mode, void *workspace, int64_t workspace_bytes,
+                     void *stream)
+{
+    int rc = validate(transa, transb, m, n, k, alpha, A, lda, B, ldb, C, ldc, mode);
+    if (rc != 0) return rc;
+    if (workspace == nullptr)
+        return run_sgemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, mode, -1,
+                         0, stream, WS_NONE);
+    if (((uintptr_t)workspace & 15u) != 0) return -15;
+    if (mode == MISGEMM_BF16X3 && m > 0 && n > 0 && k > 0 &&
+        workspace_bytes < packed_bytes(m, n, k))
+        return -16;
+    return run_sgemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, mode, -1, 0,
+                     stream, WS_CALLER, workspace, workspace_bytes);
+}
+
+int misgemm_release_workspace(void)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return MISGEMM_E_NO_DEVICE;
+    hipError_t e = hipDeviceSynchronize();
+    std::lock_guard<std::mutex> lock(g_ws_mutex);
+    DeviceWorkspace &w = g_ws[dev];
+    if (w.ptr) (void)hipFree(w.ptr);
+    for (void *p : w.retired) (void)hipFree(p);
+    w.ptr = nullptr;
+    w.bytes = 0;
+    w.retired.clear();
+    return (int)e;
+}
+
 int misgemm_num_configs(void) { return (int)configs().size(); }
 
 int misgemm_config_info(int id, misgemm_config_desc *out)
@@ -267,7 +397,7 @@ int misgemm_select_config(char transa, char transb, int64_t m, int64_t n, int64_
     int cus = 256;
     if (current_device(&dev) == 0) cus = dev->cus;
     int gm = 0;
-    return select_config(mode, ta, tb, m, n, k, cus, &gm);
+    return select_config(mode, ta, tb, m, n, k, cus, mode == MISGEMM_BF16X3, &gm);
 }
 
 int misgemm_load_tuning(const char *path)

@@ -8,6 +8,7 @@
 
 #include "../../include/misgemm.h"
 #include "gemm_tile.hpp"
+#include "packed_x3.hpp"
 
 namespace misgemm {
 
@@ -30,12 +31,14 @@ typedef hipError_t (*launch_fn)(const GemmArgs &g, int group_m, hipStream_t s);
 typedef hipError_t (*batch_launch_fn)(const ProbDev *probs, const TileDev *tiles, int64_t ntiles,
                                       int grid, hipStream_t s);
 typedef int (*occupancy_fn)();
+typedef hipError_t (*packed_launch_fn)(const PackedArgs &p, int group_m, hipStream_t s);
 
 struct ConfigEntry {
     misgemm_config_desc desc;
-    launch_fn launch[2][2];    // [transa][transb]
+    launch_fn launch[2][2];    // [transa][transb]; NULL for packed configs
     batch_launch_fn batch;     // NULL when no persistent variant is compiled
     occupancy_fn batch_occupancy;
+    packed_launch_fn packed;   // tile kernel on packed panels (packed configs only)
 };
 
 // Default number of tile-rows walked together (see tile_coords).
@@ -112,6 +115,11 @@ int batch_occupancy()
 // Registration hooks, one per translation unit.
 void register_f32(std::vector<ConfigEntry> &out);
 void register_x3(std::vector<ConfigEntry> &out);
+void register_x3k(std::vector<ConfigEntry> &out);
+
+// Pack op(X) (rows x k, KC: k contiguous) into split panels (packed_x3.hpp).
+hipError_t launch_pack(const float *X, int64_t ld, bool kc, int64_t rows, int64_t k, int vec,
+                       __bf16 *out, hipStream_t s);
 
 // Host helpers shared by the entry points.
 hipError_t launch_scale(float beta, float *C, int64_t m, int64_t n, int64_t ldc, hipStream_t s);

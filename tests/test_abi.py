@@ -121,3 +121,23 @@ def test_tuning_table_parsing(mg, tmp_path):
     # restore the packaged table, if any, for later tests
     if os.path.exists(mg.TUNING_PATH):
         mg.load_tuning(mg.TUNING_PATH)
+
+
+def test_workspace_size_and_ws_argument_checks(mg):
+    lib = mg._load()
+    # FP32 needs no workspace; bf16x3 needs 6 bytes per padded (row, k) pair
+    assert mg.workspace_size("N", "N", 1000, 1000, 1000, 0) == 0
+    w = mg.workspace_size("N", "T", 1000, 300, 100, 1)
+    kpad, mpad, npad = 112, 1024, 512
+    assert w == 6 * kpad * (mpad + npad) + 512
+    assert lib.misgemm_workspace_size(b"X", b"N", 1, 1, 1, 1) == -1
+    assert lib.misgemm_workspace_size(b"N", b"N", 1, 1, 1, 5) == -6
+    # short or misaligned caller workspace is rejected before any HIP call
+    assert lib.misgemm_sgemm_ws(b"N", b"N", 1000, 300, 100, 1.0, 0x1000, 1000, 0x2000, 100, 0.0,
+                                0x3000, 1000, 1, 0x4000, w - 1, None) == -16
+    assert lib.misgemm_sgemm_ws(b"N", b"N", 1000, 300, 100, 1.0, 0x1000, 1000, 0x2000, 100, 0.0,
+                                0x3000, 1000, 1, 0x4004, w, None) == -15
+    assert lib.misgemm_sgemm_ws(b"N", b"N", 1000, 300, 100, 1.0, 0x1000, 999, 0x2000, 100, 0.0,
+                                0x3000, 1000, 1, 0x4000, w, None) == -8
+    assert any(c["packed"] for c in mg.configs(1))
+    assert not any(c["packed"] for c in mg.configs(0))

@@ -1,6 +1,8 @@
 """GPU parity at the full workload sizes (sampled outputs checked one by one
 against the oracle), the split on its own, degenerate cases, argument errors,
 determinism and transposed-copy invariance."""
+import os
+
 import numpy as np
 import pytest
 
@@ -210,3 +212,53 @@ def test_non_default_stream():
         mg.sgemm("N", "T", p.m, p.n, p.k, 1.0, A, p.lda, B, p.ldb, 0.0, C, p.ldc, stream=s)
     s.synchronize()
     gu.check_full(p, C.cpu().numpy(), "side stream")
+
+
+def test_packed_path_caller_workspace_and_capture():
+    """The packed bf16x3 path with a caller-owned workspace: same bits as the
+    library-owned one, argument errors for a short or misaligned workspace,
+    and capture into a HIP graph (the call allocates nothing)."""
+    import torch
+    mg = _mg()
+    packed = [c for c in mg.configs(1) if c["packed"]]
+    assert packed
+    p = wl.make_problem("T", "N", 700, 520, 300, 1.5, -0.5, 123, pad=3)
+    A, B, C = gu.dev_problem(p)
+    need = mg.workspace_size("T", "N", p.m, p.n, p.k, 1)
+    assert need > 0 and mg.workspace_size("T", "N", p.m, p.n, p.k, 0) == 0
+    ws = torch.empty((need + 3) // 4, dtype=torch.float32, device="cuda")
+    ref = gu.run(p, 1, config_id=packed[0]["id"], tensors=(A, B, C)).copy()
+    gu.check_full(p, ref, "packed via library workspace")
+    mg.load_tuning(None)  # heuristics: a packed config for this bf16x3 shape
+    try:
+        assert mg.config_info(mg.select_config("T", "N", 4096, 4096, 4096, 1))["packed"] == 1
+        C.copy_(C.new_tensor(p.C0))
+        mg.sgemm_ws("T", "N", p.m, p.n, p.k, p.alpha, A, p.lda, B, p.ldb, p.beta, C, p.ldc, 1,
+                    ws, need)
+        torch.cuda.synchronize()
+        gu.check_full(p, C.cpu().numpy(), "packed via caller workspace")
+        with pytest.raises(mg.MisgemmError) as ei:
+            mg.sgemm_ws("T", "N", p.m, p.n, p.k, p.alpha, A, p.lda, B, p.ldb, p.beta, C, p.ldc,
+                        1, ws, need - 1)
+        assert ei.value.status == -16
+        with pytest.raises(mg.MisgemmError) as ei:
+            mg.sgemm_ws("T", "N", p.m, p.n, p.k, p.alpha, A, p.lda, B, p.ldb, p.beta, C, p.ldc,
+                        1, ws.data_ptr() + 4, need)
+        assert ei.value.status == -15
+        # capture: the caller workspace makes the call allocation-free
+        g = torch.cuda.CUDAGraph()
+        C.copy_(C.new_tensor(p.C0))
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            mg.sgemm_ws("T", "N", p.m, p.n, p.k, p.alpha, A, p.lda, B, p.ldb, p.beta, C, p.ldc,
+                        1, ws, need)
+        for rep in range(3):
+            C.copy_(C.new_tensor(p.C0))
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            gu.check_full(p, C.cpu().numpy(), "graph replay %d" % rep)
+    finally:
+        if os.path.exists(mg.TUNING_PATH):
+            mg.load_tuning(mg.TUNING_PATH)
+    mg.release_workspace()
