@@ -24,10 +24,16 @@ def short_name(name: str) -> str:
     if m:
         shape = "x".join(v.strip() for v in m.group(3).split(","))
         return "%s<%s %s %s>" % (m.group(1), m.group(2), shape, m.group(4).replace(" ", ""))
+    m = re.search(r"misgemm::(\w+)<misgemm::Shape<([\d, ]+)> ?>", name)
+    if m:
+        return "%s<%s>" % (m.group(1), "x".join(v.strip() for v in m.group(2).split(",")))
     m = re.search(r"misgemm::(\w+)<misgemm::[^,]*?(\w+), misgemm::Shape<([\d, ]+)>", name)
     if m:
         shape = "x".join(v.strip() for v in m.group(3).split(","))
         return "%s<%s %s>" % (m.group(1), m.group(2), shape)
+    m = re.search(r"misgemm::(\w+)<(true|false)>", name)
+    if m:
+        return "%s<%s>" % (m.group(1), m.group(2))
     m = re.search(r"misgemm::(\w+)", name)
     if m:
         return m.group(1)
