@@ -49,10 +49,24 @@ def parse():
                     help="skip the oracle leg (used under the profiler)")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched-form measurement in the default run")
+    ap.add_argument("--problem", default="",
+                    help="comma-separated problem labels: run only these problems of the "
+                         "workload (e.g. rankk128_16384x16384), for per-problem profiles")
     return ap.parse_args()
 
 
-def make_problems(workload):
+def make_problems(workload, only=""):
+    probs, desc = _workload_problems(workload)
+    if only:
+        keep = set(only.split(","))
+        probs = [p for p in probs if p.label in keep]
+        if not probs:
+            raise SystemExit("no problem of workload %s is labelled %s" % (workload, only))
+        desc += " (only %s)" % only
+    return probs, desc
+
+
+def _workload_problems(workload):
     from paper_1608_05265_amd import workloads as wl
     if workload == "square":
         return [wl.config2(s, ta, tb) for s in wl.SQUARE_SIZES for ta, tb in wl.TRANS_PAIRS], \
@@ -66,6 +80,114 @@ def make_problems(workload):
     if workload == "wide":
         return [wl.config4()], "8192^3 NN, alpha=1, beta=0, entries random sign x 2^U[-8,8]"
     raise ValueError(workload)
+
+
+class ClockSampler:
+    """Samples the GPU's graphics clock (MHz, mean over the XCDs) and socket
+    power (W) from the SMU metrics table through amdsmi on a host thread
+    every `period` seconds, and the share of the interval spent at the
+    package power limit (PPT residency).  Fields stay None where amdsmi is
+    missing or refuses."""
+
+    def __init__(self, period=0.05, skip=0.5):
+        self.period = period
+        self.skip = skip
+        self.clk = []
+        self.power = []
+        self.first = None
+        self.last = None
+        self.error = None
+        self._stop = None
+        self._thread = None
+        self._h = None
+        self._amdsmi = None
+
+    @staticmethod
+    def _num(v):
+        return float(v) if isinstance(v, (int, float)) and 0 < v < 1e15 else None
+
+    def _read(self, keep):
+        try:
+            m = self._amdsmi.amdsmi_get_gpu_metrics_info(self._h)
+        except Exception as e:  # noqa: BLE001 - report, do not fail the bench
+            self.error = "metrics: %s" % type(e).__name__
+            return
+        clks = [self._num(c) for c in (m.get("current_gfxclks") or [])]
+        clks = [c for c in clks if c is not None and c < 10000]
+        pw = self._num(m.get("current_socket_power"))
+        acc = (self._num(m.get("accumulation_counter")), self._num(m.get("ppt_residency_acc")))
+        if keep:
+            if clks:
+                self.clk.append(sum(clks) / len(clks))
+            if pw is not None:
+                self.power.append(pw)
+            if self.first is None:
+                self.first = acc
+            self.last = acc
+
+    def _loop(self):
+        import time as _t
+        t0 = _t.perf_counter()
+        while not self._stop.wait(self.period):
+            self._read(_t.perf_counter() - t0 >= self.skip)
+
+    def __enter__(self):
+        import threading
+        try:
+            import amdsmi
+            amdsmi.amdsmi_init()
+            self._h = amdsmi.amdsmi_get_processor_handles()[0]
+            self._amdsmi = amdsmi
+        except Exception as e:  # noqa: BLE001
+            self.error = "amdsmi unavailable: %s" % type(e).__name__
+            return self
+        self._stop = threading.Event()
+        self._thread = threading.Thread(target=self._loop, daemon=True)
+        self._thread.start()
+        return self
+
+    def __exit__(self, *exc):
+        if self._thread is not None:
+            self._stop.set()
+            self._thread.join()
+            try:
+                self._amdsmi.amdsmi_shut_down()
+            except Exception:  # noqa: BLE001
+                pass
+        return False
+
+    def summary(self):
+        def stats(v):
+            if not v:
+                return None
+            v = sorted(v)
+            return {"median": round(v[len(v) // 2], 1), "min": round(v[0], 1),
+                    "max": round(v[-1], 1), "samples": len(v)}
+        out = {"sclk_mhz": stats(self.clk), "socket_power_w": stats(self.power),
+               "ppt_residency": None}
+        if self.first and self.last and None not in self.first + self.last:
+            d_acc = self.last[0] - self.first[0]
+            if d_acc > 0:
+                out["ppt_residency"] = round((self.last[1] - self.first[1]) / d_acc, 3)
+        if self.error:
+            out["note"] = self.error
+        return out
+
+
+def clock_probe(torch, fn, seconds=2.5):
+    """Run `fn` (which enqueues GPU work) back to back for about `seconds`
+    while sampling clock and power; the first half second is not sampled so
+    that the readings describe the loaded steady state."""
+    with ClockSampler() as clock:
+        t0 = time.perf_counter()
+        n = 0
+        while time.perf_counter() - t0 < seconds:
+            fn()
+            n += 1
+            if n % 4 == 0:
+                torch.cuda.synchronize()
+        torch.cuda.synchronize()
+    return clock.summary()
 
 
 class Resident:
@@ -116,6 +238,28 @@ def time_steps(torch, res, mg, mode, steps, warmup, dominant):
     return total, durs
 
 
+def latency(torch, r, mg, mode, calls=1000):
+    """Per-call latency of one small problem: `calls` calls each bracketed
+    by events on the launching stream (median and minimum of the event
+    times), then `calls` calls back to back (host wall time per call)."""
+    stream = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(calls)]
+    for s, e in evs:
+        s.record(stream)
+        r.call(mg, mode)
+        e.record(stream)
+    torch.cuda.synchronize()
+    d = sorted(s.elapsed_time(e) * 1e3 for s, e in evs)
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        r.call(mg, mode)
+    torch.cuda.synchronize()
+    b2b = (time.perf_counter() - t0) / calls * 1e6
+    return {"median_us": round(d[calls // 2], 3), "min_us": round(d[0], 3),
+            "back_to_back_us": round(b2b, 3), "calls": calls}
+
+
 def cpu_baseline_leg(res, mg, torch, workload):
     """The FP64 oracle timed on a bounded sample of the same inputs, on the
     host's cores; the same sample gives the error of the GPU results."""
@@ -156,6 +300,15 @@ def cpu_baseline_leg(res, mg, torch, workload):
             e["within_bound"] = e["within_bound"] and bool(ok)
     out["value"] = total_flops / total_dt / 1e12
     out["seconds"] = total_dt
+    if workload == "c1":
+        # the paper's host reference ran on one core: the same oracle on one thread
+        p = picks[0].p
+        t0 = time.perf_counter()
+        oracle.sgemm_f64(p.transa, p.transb, p.m, p.n, p.k, p.alpha, p.A, p.lda, p.B, p.ldb,
+                         p.beta, p.C0, p.ldc, nthreads=1)
+        dt1 = time.perf_counter() - t0
+        out["single_thread"] = {"value": 2.0 * p.m * p.n * p.k / dt1 / 1e12, "cores": 1,
+                                "seconds": dt1}
     out["sample"] = ("full FP64 oracle (C and |A||B|) of the %d problems %s of the workload, "
                      "the same inputs as the GPU run; rate = sum 2MNK / time"
                      % (len(picks), ",".join(r.p.label for r in picks)))
@@ -213,6 +366,7 @@ def batch_measure(torch, mg, problems, mode, steps, warmup):
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
     durs = [s.elapsed_time(e) for s, e in evs]
+    info["clock"] = clock_probe(torch, g.replay, seconds=1.5)
     return res, plan, info, total, durs
 
 
@@ -261,7 +415,8 @@ def batch_line(args, torch, mg):
                      "launch_avg_ms": avg,
                      "launch_tflops": flops / (avg * 1e-3) / 1e12,
                      "config": cfg["name"], "tiles": info["tiles"], "grid": info["grid"],
-                     "tile_efficiency": info["flops"] / info["tile_flops"]}
+                     "tile_efficiency": info["flops"] / info["tile_flops"],
+                     "clock": info["clock"]}
         if not args.no_cpu_baseline:
             err, oflops, odt = batch_errors(torch, mg, res, plan, cores)
             out[name]["error"] = err
@@ -303,7 +458,8 @@ def batch_line(args, torch, mg):
 
 COPY_BYTES = 1 << 30
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sgemm_dominant8192_hbm_counters.txt")
-KERNEL_SOURCES = ["gemm_tile.hpp", "registry.hpp", "sgemm_f32.hip", "sgemm_x3.hip"]
+KERNEL_SOURCES = ["gemm_tile.hpp", "packed_x3.hpp", "registry.hpp", "aux_kernels.hip",
+                  "sgemm_f32.hip", "sgemm_x3.hip", "sgemm_x3k.hip"]
 
 
 def kernel_sources_hash() -> str:
@@ -367,7 +523,7 @@ def main():
     if args.workload == "dominant":
         dominant_only(args, torch, mg)
         return
-    problems, desc = make_problems(args.workload)
+    problems, desc = make_problems(args.workload, args.problem)
     res = [Resident(p, dev) for p in problems]
     torch.cuda.synchronize()
     flops_step = sum(2.0 * r.p.m * r.p.n * r.p.k for r in res)
@@ -386,7 +542,8 @@ def main():
                         "dominant_tflops": per_launch / (avg_ms * 1e-3) / 1e12,
                         "dominant": "%dx%dx%d (%s)" % (dp.m, dp.n, dp.k,
                                                        ",".join(res[i].p.transa + res[i].p.transb
-                                                                for i in dominant))}
+                                                                for i in dominant)),
+                        "clock": clock_probe(torch, lambda: res[dominant[0]].call(mg, mode))}
     # per-problem rates (one extra timed pass each, after the timed region)
     per_problem = []
     for r in res:
@@ -403,6 +560,9 @@ def main():
             torch.cuda.synchronize()
             ms = s.elapsed_time(e) / reps
             row[name + "_tflops"] = round(2.0 * r.p.m * r.p.n * r.p.k / ms / 1e9, 2)
+        if args.workload == "c1":
+            for mode, name in ((mg.FP32, "fp32"), (mg.BF16X3, "bf16x3")):
+                row[name + "_latency"] = latency(torch, r, mg, mode)
         per_problem.append(row)
 
     f32 = result["fp32"]
@@ -445,6 +605,7 @@ def main():
             "algorithmic_bytes_per_launch": 4.0 * (dp.m * dp.k + dp.k * dp.n + 2 * dp.m * dp.n),
         },
         "per_problem": per_problem,
+        "clock": {"fp32": f32["clock"], "bf16x3": x3["clock"]},
     }
     if not args.no_cpu_baseline:
         cpu, errors = cpu_baseline_leg(res, mg, torch, args.workload)

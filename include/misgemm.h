@@ -195,8 +195,11 @@ typedef struct misgemm_batch misgemm_batch; /* opaque plan */
 
 /*
  * Validate `count` problems, cut every one into C tiles of the chosen
- * configuration, order the tiles by decreasing work (longest first), and
- * upload the problem and tile tables to device memory owned by the plan.
+ * configuration, deal the tiles to one list per XCD (problems cut into
+ * chunks of consecutive tiles, chunks placed longest first on the least
+ * loaded list, so each XCD's L2 serves few problems), order every list by
+ * decreasing work (longest first), and upload the problem and tile tables
+ * to device memory owned by the plan.
  * config_id < 0 picks the configuration from the tuning table / heuristics.
  * On a bad problem returns that problem's argument error (negative, as for
  * misgemm_sgemm) or MISGEMM_E_BATCH and stores its index in *bad_index.
@@ -216,12 +219,15 @@ int misgemm_batch_plan(const misgemm_problem *problems, int64_t count, int mode,
  */
 int misgemm_batch_launch(const misgemm_batch *plan, void *stream);
 
-/* Plan facts: tiles, workgroups launched, config id, total flops 2*m*n*k. */
+/* Plan facts: tiles, workgroups launched, config id, total flops 2*m*n*k,
+ * and the partition of the tiles over the XCDs. */
 typedef struct {
     int64_t count, tiles, grid;
     int config_id;
     double flops;
-    double tile_flops; /* flops of whole tiles, edges padded (>= flops) */
+    double tile_flops;     /* flops of whole tiles, edges padded (>= flops) */
+    int parts;             /* tile lists, one per XCD (1 for tiny batches) */
+    double part_imbalance; /* largest list's work / mean list work (>= 1) */
 } misgemm_batch_desc;
 
 int misgemm_batch_info(const misgemm_batch *plan, misgemm_batch_desc *out);

@@ -58,7 +58,8 @@ class Problem(ctypes.Structure):
 class BatchDesc(ctypes.Structure):
     _fields_ = [("count", ctypes.c_int64), ("tiles", ctypes.c_int64), ("grid", ctypes.c_int64),
                 ("config_id", ctypes.c_int), ("flops", ctypes.c_double),
-                ("tile_flops", ctypes.c_double)]
+                ("tile_flops", ctypes.c_double), ("parts", ctypes.c_int),
+                ("part_imbalance", ctypes.c_double)]
 
 
 def library_path() -> str:
@@ -262,7 +263,8 @@ class Batch:
         d = BatchDesc()
         _check(_load().misgemm_batch_info(self._h, ctypes.byref(d)), "misgemm_batch_info")
         return {"count": d.count, "tiles": d.tiles, "grid": d.grid, "config_id": d.config_id,
-                "flops": d.flops, "tile_flops": d.tile_flops}
+                "flops": d.flops, "tile_flops": d.tile_flops, "parts": d.parts,
+                "part_imbalance": d.part_imbalance}
 
     def destroy(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value is not None:

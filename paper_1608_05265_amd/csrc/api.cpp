@@ -302,6 +302,8 @@ struct misgemm_batch {
     int64_t count, ntiles;
     int grid;
     double flops, tile_flops;
+    double part_imbalance;
+    BatchSplit split;
     ProbDev *d_probs;
     TileDev *d_tiles;
     int device;
@@ -503,7 +505,8 @@ int misgemm_batch_plan(const misgemm_problem *problems, int64_t count, int mode,
 
     std::vector<ProbDev> probs;
     std::vector<TileDev> tiles;
-    std::vector<int64_t> work;  // per-tile K (work of a full tile is bm*bn*k)
+    std::vector<int64_t> work;   // per-tile K (work of a full tile is bm*bn*k)
+    std::vector<int64_t> first;  // per problem: index of its first tile
     probs.reserve((size_t)count);
     double flops = 0.0, tile_flops = 0.0;
     for (int64_t i = 0; i < count; ++i) {
@@ -530,6 +533,7 @@ int misgemm_batch_plan(const misgemm_problem *problems, int64_t count, int mode,
         }
         const int32_t idx = (int32_t)probs.size();
         probs.push_back(pd);
+        first.push_back((int64_t)tiles.size());
         flops += 2.0 * (double)p.m * (double)p.n * (double)pd.g.k;
         tile_flops += 2.0 * (double)(pd.tiles_m * d.bm) * (double)(pd.tiles_n * d.bn) *
                       (double)pd.g.k;
@@ -539,13 +543,63 @@ int misgemm_batch_plan(const misgemm_problem *problems, int64_t count, int mode,
                 work.push_back(pd.g.k);
             }
     }
-    // longest-processing-time-first order (stable, so tiles of one problem stay together)
-    std::vector<size_t> order(tiles.size());
-    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](size_t a, size_t b) { return work[a] > work[b]; });
-    std::vector<TileDev> sorted(tiles.size());
-    for (size_t i = 0; i < order.size(); ++i) sorted[i] = tiles[order[i]];
+    first.push_back((int64_t)tiles.size());
+    const int64_t ntiles = (int64_t)tiles.size();
+    const int occ = table[cfg].batch_occupancy ? table[cfg].batch_occupancy() : 1;
+    int64_t grid = (int64_t)dev->cus * occ;
+    if (grid > ntiles) grid = ntiles;
+    if (grid < 1) grid = 1;
+    const int nx = grid >= MAX_XCD ? MAX_XCD : 1;
+    grid -= grid % nx;
+
+    // Deal the tiles to the XCDs so that each XCD's L2 serves few problems:
+    // problems are cut into chunks of consecutive tiles (tiles of a chunk
+    // share operand panels) of at most 1/(4*nx) of the total work, the
+    // chunks go longest first to the least-loaded XCD, and each XCD orders
+    // its tiles by decreasing K (longest processing time first; stable, so
+    // the tiles of a chunk stay together).
+    int64_t total_work = 0;
+    for (int64_t w : work) total_work += std::max<int64_t>(1, w);
+    const int64_t chunk_cap = std::max<int64_t>(1, (total_work + 4 * nx - 1) / (4 * nx));
+    struct Chunk { int64_t begin, end, work; };
+    std::vector<Chunk> chunks;
+    for (size_t p = 0; p + 1 < first.size(); ++p) {
+        const int64_t b = first[p], e = first[p + 1];
+        if (b == e) continue;
+        const int64_t per = std::max<int64_t>(1, work[(size_t)b]);
+        const int64_t pwork = (e - b) * per;
+        const int64_t pieces = (pwork + chunk_cap - 1) / chunk_cap;
+        const int64_t step = (e - b + pieces - 1) / pieces;
+        for (int64_t c = b; c < e; c += step) {
+            const int64_t ce = std::min(e, c + step);
+            chunks.push_back({c, ce, (ce - c) * per});
+        }
+    }
+    std::stable_sort(chunks.begin(), chunks.end(),
+                     [](const Chunk &a, const Chunk &b) { return a.work > b.work; });
+    std::vector<std::vector<int64_t>> part((size_t)nx);
+    std::vector<int64_t> load((size_t)nx, 0);
+    for (const Chunk &c : chunks) {
+        int best = 0;
+        for (int x = 1; x < nx; ++x)
+            if (load[(size_t)x] < load[(size_t)best]) best = x;
+        load[(size_t)best] += c.work;
+        for (int64_t t = c.begin; t < c.end; ++t) part[(size_t)best].push_back(t);
+    }
+    std::vector<TileDev> sorted;
+    sorted.reserve(tiles.size());
+    BatchSplit split = {};
+    split.nx = nx;
+    int64_t max_load = 0;
+    for (int x = 0; x < nx; ++x) {
+        std::vector<int64_t> &pt = part[(size_t)x];
+        std::stable_sort(pt.begin(), pt.end(),
+                         [&](int64_t a, int64_t b) { return work[(size_t)a] > work[(size_t)b]; });
+        split.off[x] = (int64_t)sorted.size();
+        for (int64_t t : pt) sorted.push_back(tiles[(size_t)t]);
+        max_load = std::max(max_load, load[(size_t)x]);
+    }
+    for (int x = nx; x <= MAX_XCD; ++x) split.off[x] = (int64_t)sorted.size();
 
     misgemm_batch *b = (misgemm_batch *)calloc(1, sizeof(misgemm_batch));
     if (!b) return (int)hipErrorOutOfMemory;
@@ -555,11 +609,9 @@ int misgemm_batch_plan(const misgemm_problem *problems, int64_t count, int mode,
     b->ntiles = (int64_t)sorted.size();
     b->flops = flops;
     b->tile_flops = tile_flops;
+    b->split = split;
+    b->part_imbalance = total_work > 0 ? (double)max_load * nx / (double)total_work : 1.0;
     hipGetDevice(&b->device);
-    const int occ = table[cfg].batch_occupancy ? table[cfg].batch_occupancy() : 1;
-    int64_t grid = (int64_t)dev->cus * occ;
-    if (grid > b->ntiles) grid = b->ntiles;
-    if (grid < 1) grid = 1;
     b->grid = (int)grid;
     hipError_t e = hipSuccess;
     if (!probs.empty()) {
@@ -587,7 +639,7 @@ int misgemm_batch_launch(const misgemm_batch *plan, void *stream)
     if (plan == nullptr) return MISGEMM_E_NULL_PLAN;
     if (plan->ntiles == 0) return 0;
     const ConfigEntry &c = configs()[plan->config_id];
-    return (int)c.batch(plan->d_probs, plan->d_tiles, plan->ntiles, plan->grid,
+    return (int)c.batch(plan->d_probs, plan->d_tiles, plan->split, plan->grid,
                         (hipStream_t)stream);
 }
 
@@ -601,6 +653,8 @@ int misgemm_batch_info(const misgemm_batch *plan, misgemm_batch_desc *out)
     out->config_id = plan->config_id;
     out->flops = plan->flops;
     out->tile_flops = plan->tile_flops;
+    out->parts = plan->split.nx;
+    out->part_imbalance = plan->part_imbalance;
     return 0;
 }
 

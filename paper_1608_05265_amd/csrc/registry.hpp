@@ -27,9 +27,19 @@ struct TileDev {
     int32_t pad;
 };
 
+// Partition of a batch's tile list over the XCDs: the workgroups of XCD x
+// (blockIdx % nx == x, the hardware hands workgroups to the XCDs in turn)
+// run tiles[off[x] .. off[x+1]).  nx is 1 (one shared list) or MAX_XCD.
+constexpr int MAX_XCD = 8;
+struct BatchSplit {
+    int64_t off[MAX_XCD + 1];
+    int32_t nx;
+    int32_t pad;
+};
+
 typedef hipError_t (*launch_fn)(const GemmArgs &g, int group_m, hipStream_t s);
-typedef hipError_t (*batch_launch_fn)(const ProbDev *probs, const TileDev *tiles, int64_t ntiles,
-                                      int grid, hipStream_t s);
+typedef hipError_t (*batch_launch_fn)(const ProbDev *probs, const TileDev *tiles,
+                                      const BatchSplit &split, int grid, hipStream_t s);
 typedef int (*occupancy_fn)();
 typedef hipError_t (*packed_launch_fn)(const PackedArgs &p, int group_m, hipStream_t s);
 
@@ -73,13 +83,18 @@ struct MaxI { static constexpr int value = A > B ? A : B; };
 template <template <class, bool, bool> class TILE, class SH>
 __global__ __launch_bounds__(SH::NT, 1) void batch_kernel(const ProbDev *__restrict__ probs,
                                                           const TileDev *__restrict__ tiles,
-                                                          int64_t ntiles)
+                                                          BatchSplit split)
 {
     constexpr int L0 = TILE<SH, false, false>::LDS_BYTES, L1 = TILE<SH, false, true>::LDS_BYTES;
     constexpr int L2 = TILE<SH, true, false>::LDS_BYTES, L3 = TILE<SH, true, true>::LDS_BYTES;
     __shared__ __attribute__((aligned(16)))
     char smem[MaxI<MaxI<L0, L1>::value, MaxI<L2, L3>::value>::value];
-    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    // The grid is a multiple of nx: every XCD has gridDim.x / nx slots, and
+    // slot s of XCD x runs tiles off[x] + s, off[x] + s + slots, ...
+    const int x = (int)(blockIdx.x % (unsigned)split.nx);
+    const int64_t slot = blockIdx.x / (unsigned)split.nx, slots = gridDim.x / (unsigned)split.nx;
+    const int64_t end = split.off[x + 1];
+    for (int64_t t = split.off[x] + slot; t < end; t += slots) {
         const TileDev td = tiles[t];
         const ProbDev &p = probs[td.prob];
         const GemmArgs g = p.g;
@@ -94,11 +109,11 @@ __global__ __launch_bounds__(SH::NT, 1) void batch_kernel(const ProbDev *__restr
 }
 
 template <template <class, bool, bool> class TILE, class SH>
-hipError_t launch_batch_kernel(const ProbDev *probs, const TileDev *tiles, int64_t ntiles,
+hipError_t launch_batch_kernel(const ProbDev *probs, const TileDev *tiles, const BatchSplit &split,
                                int grid, hipStream_t s)
 {
     hipLaunchKernelGGL((batch_kernel<TILE, SH>), dim3(grid), dim3(SH::NT), 0, s, probs, tiles,
-                       ntiles);
+                       split);
     return hipGetLastError();
 }
 

@@ -66,6 +66,9 @@ def test_batch512_graph_replay(mode):
     plan = mg.Batch(descs, mode=mode)
     info = plan.info()
     assert info["count"] == 512 and info["tiles"] > 0
+    # one tile list per XCD, close to even work
+    assert info["parts"] == 8 and info["grid"] % 8 == 0
+    assert 1.0 <= info["part_imbalance"] < 1.05
     plan.launch()
     torch.cuda.synchronize()
     _check_all(problems, dev, False, "batch512 mode %d" % mode)
@@ -92,6 +95,38 @@ def test_batch512_graph_replay(mode):
             assert torch.equal(C.view(torch.int32), e.view(torch.int32)), (rep, idx)
         scratch.mul_(1.0001).add_(1.0)  # unrelated eager work between replays
         torch.cuda.synchronize()
+    plan.destroy()
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["fp32", "bf16x3"])
+def test_batch_skewed_work_is_split_over_xcds(mode):
+    """One problem carrying most of the work beside small ones: it is cut
+    into chunks spread over the XCD lists (not left to one XCD), and every
+    problem is still computed right."""
+    import torch
+    import paper_1608_05265_amd as mg
+    problems = [wl.make_problem("N", "T", 1536, 1280, 384, 1.0, 0.5, 21, pad=2)]
+    problems += wl.config5(count=24, seed_case=8, lo=1, hi=12, step=5)
+    problems.append(wl.make_problem("T", "N", 8, 8, 8, 1.0, 0.0, 22))  # fewer tiles than XCDs
+    dev, c0, descs = _setup(problems)
+    plan = mg.Batch(descs, mode=mode)
+    info = plan.info()
+    assert info["parts"] == 8
+    assert info["part_imbalance"] < 1.35, info
+    plan.launch()
+    torch.cuda.synchronize()
+    _check_all(problems, dev, False, "skewed mode %d" % mode)
+    plan.destroy()
+
+    # a batch with fewer tiles than XCDs runs from one list
+    tiny = [wl.make_problem("N", "N", 16, 16, 16, 1.0, 0.0, 23 + i) for i in range(3)]
+    dev, c0, descs = _setup(tiny)
+    plan = mg.Batch(descs, mode=mode)
+    info = plan.info()
+    assert info["parts"] == 1 and info["grid"] >= 1
+    plan.launch()
+    torch.cuda.synchronize()
+    _check_all(tiny, dev, True, "tiny mode %d" % mode)
     plan.destroy()
 
 
