@@ -42,13 +42,15 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="square",
-                    choices=["square", "c1", "rankk", "wide", "batch", "dominant"],
+                    choices=["square", "c1", "rankk", "wide", "batch", "dominant", "peak"],
                     help="dominant: only the 8192^3 NN problem of the square sweep in both "
                          "forms plus a 1 GiB device copy, for counter collection")
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle leg (used under the profiler)")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched-form measurement in the default run")
+    ap.add_argument("--no-peak", action="store_true",
+                    help="skip the matrix-core rate probe in the default run")
     ap.add_argument("--problem", default="",
                     help="comma-separated problem labels: run only these problems of the "
                          "workload (e.g. rankk128_16384x16384), for per-problem profiles")
@@ -188,6 +190,56 @@ def clock_probe(torch, fn, seconds=2.5):
                 torch.cuda.synchronize()
         torch.cuda.synchronize()
     return clock.summary()
+
+
+PROBE_FLOP = {0: 32 * 32 * 2 * 2, 1: 32 * 32 * 16 * 2}   # per MFMA: 32x32x2 f32, 32x32x16 bf16
+
+
+def measure_peaks(torch, seconds=2.5):
+    """Sustained matrix-core rate of this GPU (the probe library: four
+    independent accumulators per wave, two waves per SIMD, back-to-back
+    MFMAs), with random and with zero operands, each after `seconds` of
+    back-to-back launches so that clock and power have settled; the clock,
+    power and PPT residency of that interval come with each rate."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_1608_05265_amd", "libmisgemm_probe.so"))
+    lib.probe_mfma_launch.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+    lib.probe_mfma_launch.restype = ctypes.c_int
+    dev = torch.device("cuda:0")
+    blocks = torch.cuda.get_device_properties(0).multi_processor_count * 2
+    out = torch.empty(blocks * 256, device=dev)
+    gen = torch.Generator().manual_seed(1608)
+    stream = torch.cuda.current_stream()
+    res = {}
+    for kind, name, iters in ((0, "fp32", 8000), (1, "bf16", 16000)):
+        dt = torch.float32 if kind == 0 else torch.bfloat16
+        for data in ("random", "zero"):
+            ops = ((torch.rand(4096, generator=gen) * 2 - 1).to(dt) if data == "random"
+                   else torch.zeros(4096, dtype=dt)).to(dev)
+
+            def launch():
+                rc = lib.probe_mfma_launch(kind, ops.data_ptr(), out.data_ptr(), iters, blocks,
+                                           stream.cuda_stream)
+                if rc != 0:
+                    raise RuntimeError("probe launch failed: %d" % rc)
+            launch()
+            torch.cuda.synchronize()
+            clock = clock_probe(torch, launch, seconds=seconds)
+            evs = []
+            for _ in range(15):
+                s_ = torch.cuda.Event(enable_timing=True)
+                e_ = torch.cuda.Event(enable_timing=True)
+                s_.record(stream)
+                launch()
+                e_.record(stream)
+                evs.append((s_, e_))
+            torch.cuda.synchronize()
+            ms = sorted(a.elapsed_time(b) for a, b in evs)[7]
+            flops = blocks * 4 * iters * 4 * PROBE_FLOP[kind]
+            res["%s_%s" % (name, data)] = {"tflops": round(flops / (ms * 1e-3) / 1e12, 1),
+                                           "clock": clock}
+    return res
 
 
 class Resident:
@@ -523,6 +575,11 @@ def main():
     if args.workload == "dominant":
         dominant_only(args, torch, mg)
         return
+    if args.workload == "peak":
+        print(json.dumps({"workload": "peak", "spec_tflops": {"fp32": PEAK_FP32,
+                                                             "bf16": PEAK_BF16},
+                          "measured": measure_peaks(torch)}))
+        return
     problems, desc = make_problems(args.workload, args.problem)
     res = [Resident(p, dev) for p in problems]
     torch.cuda.synchronize()
@@ -611,6 +668,14 @@ def main():
         cpu, errors = cpu_baseline_leg(res, mg, torch, args.workload)
         line["cpu_baseline"] = cpu
         line["error"] = errors
+    if args.workload == "square" and not args.no_peak:
+        peaks = measure_peaks(torch)
+        line["measured_peak"] = peaks
+        fp = peaks["fp32_random"]["tflops"]
+        line["roofline"]["measured_peak"] = fp
+        line["roofline"]["frac_of_measured_peak"] = round(f32["dominant_tflops"] / fp, 4)
+        line["bf16x3"]["pct_of_measured_bf16_peak"] = round(
+            100.0 * 6 * x3["tflops"] / peaks["bf16_random"]["tflops"], 2)
     if args.workload == "square" and not args.no_batch:
         del res
         torch.cuda.empty_cache()

@@ -74,9 +74,18 @@ typedef enum {
  * mode: a misgemm_mode.
  * Errors: -1 transa, -2 transb, -3 m, -4 n, -5 k, -7 A NULL with work to do,
  *   -8 lda, -9 B NULL, -10 ldb, -12 C NULL, -13 ldc, -14 mode.
- * The kernel configuration (tile shape, wave layout) comes from the loaded
- * tuning table when it holds an entry for the shape, else from built-in
- * heuristics.  Allocates nothing.
+ * The kernel configuration (tile shape, wave layout, split-K factor) comes
+ * from the loaded tuning table when it holds an entry for the shape, else
+ * from built-in heuristics.  Two choices use scratch memory that the library
+ * owns per (device, stream) -- calls on one stream share it in stream order,
+ * calls on different streams never share it: the packed bf16x3
+ * configurations (see misgemm_sgemm_ws) and split-K, which the heuristics
+ * pick when the C tiles alone would leave CUs idle (each of `splits`
+ * workgroups per tile computes a K range and stores its partial tile; a
+ * second kernel adds the partials in split order and applies alpha/beta, so
+ * results are reproducible bit for bit).
+ * The scratch is allocated on first need and never while the stream is
+ * being captured (the call then runs without it).
  */
 int misgemm_sgemm(char transa, char transb, int64_t m, int64_t n, int64_t k,
                   float alpha, const float *A, int64_t lda,
@@ -100,6 +109,25 @@ int misgemm_sgemm_config(char transa, char transb, int64_t m, int64_t n, int64_t
                          int mode, int config_id, int group_m, void *stream);
 
 /*
+ * misgemm_sgemm_config with an explicit split-K factor (the GPU form of the
+ * partial results the paper sums on the host, Section III-C): splits in
+ * [1, 64]; 1 runs the whole K range in every workgroup (as
+ * misgemm_sgemm_config), larger values cut K into that many whole-BK ranges
+ * (fewer when K has fewer blocks).  config_id < 0 with splits > 1 picks the
+ * split-capable configuration of the mode with the smallest tile.  Uses the
+ * library scratch of (device, stream) for splits * tiles * bm * bn * 4 bytes
+ * of partial tiles; two kernel launches.  Errors as misgemm_sgemm_config,
+ * plus -17 for splits outside [1, 64], MISGEMM_E_BAD_CONFIG for a
+ * configuration without a split-K variant, MISGEMM_E_CAPTURING when the
+ * scratch would have to be allocated during capture.
+ */
+int misgemm_sgemm_split(char transa, char transb, int64_t m, int64_t n, int64_t k,
+                        float alpha, const float *A, int64_t lda,
+                        const float *B, int64_t ldb,
+                        float beta, float *C, int64_t ldc,
+                        int mode, int config_id, int group_m, int splits, void *stream);
+
+/*
  * Workspace for the packed bf16x3 path.  Packed configurations first split
  * op(A) and op(B) into bf16 panels (the BLIS packing step: for each block of
  * 16 k, each of the three parts, each row, 16 consecutive values), then run
@@ -115,14 +143,16 @@ int misgemm_sgemm_config(char transa, char transb, int64_t m, int64_t n, int64_t
  *   misgemm_workspace_size (-16 if not, -15 if misaligned) and the call
  *   allocates nothing (capturable).  The workspace must not be reused by
  *   another call before this one completes on `stream`.
+ * misgemm_sgemm_ws never uses split-K.
  * misgemm_sgemm itself, in MISGEMM_BF16X3 mode with a packed configuration
- *   selected, uses a workspace the library owns per device: grown with
- *   hipMalloc when a larger problem arrives (never while the stream is being
- *   captured; then a non-packed configuration is used instead).  Buffers are
- *   kept, including outgrown ones that earlier captured graphs may still
- *   reference, until misgemm_release_workspace().
+ *   selected, uses a workspace the library owns per (device, stream): grown
+ *   with hipMalloc when a larger problem arrives (never while the stream is
+ *   being captured; then a non-packed configuration is used instead).
+ *   Buffers are kept, including outgrown ones that earlier captured graphs
+ *   may still reference, until misgemm_release_workspace().
  * misgemm_release_workspace: synchronizes the current device and frees the
- *   library-owned workspaces of that device.
+ *   library-owned scratch of that device (all streams); graphs captured
+ *   with it must not be replayed afterwards.
  */
 int64_t misgemm_workspace_size(char transa, char transb, int64_t m, int64_t n, int64_t k,
                                int mode);
@@ -142,6 +172,7 @@ typedef struct {
     int lds_bytes;     /* LDS used per workgroup                        */
     int packed;        /* 1: operands are first split into packed panels
                           in a workspace (bf16x3 only), 0: split in LDS  */
+    int splitk;        /* 1: a split-K variant is compiled               */
     char name[48];     /* e.g. "fp32p_256x256x16_w128x64"              */
 } misgemm_config_desc;
 
@@ -161,9 +192,11 @@ int misgemm_select_config(char transa, char transb, int64_t m, int64_t n, int64_
 /*
  * Load the tuning table written by the autotuner.  Text file: the header
  * line "misgemm-tuning 1", then lines
- *     <mode> <transa> <transb> <m> <n> <k> <config_name> [<group_m>]
+ *     <mode> <transa> <transb> <m> <n> <k> <config_name> [<group_m> [<splits>]]
  * (a problem is served by the entry of its mode and transposes whose sizes
- * are all within a factor 2 of its own, nearest in summed log-distance) and
+ * are all within a factor 2 of its own, nearest in summed log-distance;
+ * splits 0 or absent = automatic, 1 = none, >= 2 needs a configuration with
+ * a split-K variant) and
  *     batch <mode> <config_name>
  * (the default configuration of batched plans); '#' starts a comment line.
  * path == NULL clears the table and returns to the built-in heuristics.

@@ -44,7 +44,7 @@ class ConfigDesc(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("bm", ctypes.c_int), ("bn", ctypes.c_int),
                 ("bk", ctypes.c_int), ("wm", ctypes.c_int), ("wn", ctypes.c_int),
                 ("threads", ctypes.c_int), ("lds_bytes", ctypes.c_int),
-                ("packed", ctypes.c_int), ("name", ctypes.c_char * 48)]
+                ("packed", ctypes.c_int), ("splitk", ctypes.c_int), ("name", ctypes.c_char * 48)]
 
 
 class Problem(ctypes.Structure):
@@ -81,6 +81,8 @@ def _load():
     lib.misgemm_sgemm.restype = i32
     lib.misgemm_sgemm_config.argtypes = sig + [i32, i32, vp]
     lib.misgemm_sgemm_config.restype = i32
+    lib.misgemm_sgemm_split.argtypes = sig + [i32, i32, i32, vp]
+    lib.misgemm_sgemm_split.restype = i32
     lib.misgemm_sgemm_ws.argtypes = sig + [vp, i64, vp]
     lib.misgemm_sgemm_ws.restype = i32
     lib.misgemm_workspace_size.argtypes = [c, c, i64, i64, i64, i32]
@@ -169,6 +171,17 @@ def sgemm_config(transa: str, transb: str, m: int, n: int, k: int, alpha: float,
     _check(rc, "misgemm_sgemm_config")
 
 
+def sgemm_split(transa: str, transb: str, m: int, n: int, k: int, alpha: float, A, lda: int,
+                B, ldb: int, beta: float, C, ldc: int, mode, config_id: int = -1,
+                group_m: int = 0, splits: int = 1, stream=None) -> None:
+    """sgemm with an explicit split-K factor (config_id -1: the split-capable
+    configuration with the smallest tile)."""
+    rc = _load().misgemm_sgemm_split(transa.encode(), transb.encode(), m, n, k, alpha, _ptr(A),
+                                     lda, _ptr(B), ldb, beta, _ptr(C), ldc, _mode(mode),
+                                     config_id, group_m, splits, _stream(stream))
+    _check(rc, "misgemm_sgemm_split")
+
+
 def sgemm_ws(transa: str, transb: str, m: int, n: int, k: int, alpha: float, A, lda: int, B,
              ldb: int, beta: float, C, ldc: int, mode, workspace, workspace_bytes: int,
              stream=None) -> None:
@@ -199,7 +212,7 @@ def config_info(config_id: int) -> dict:
     _check(_load().misgemm_config_info(config_id, ctypes.byref(d)), "misgemm_config_info")
     return {"id": config_id, "mode": d.mode, "bm": d.bm, "bn": d.bn, "bk": d.bk, "wm": d.wm,
             "wn": d.wn, "threads": d.threads, "lds_bytes": d.lds_bytes,
-            "packed": d.packed, "name": d.name.decode()}
+            "packed": d.packed, "splitk": d.splitk, "name": d.name.decode()}
 
 
 def configs(mode=None) -> List[dict]:

@@ -5,8 +5,10 @@
 For every tuning key (mode, transposes, m, n, k) every compiled
 configuration of that mode is timed through the C-ABI
 (misgemm_sgemm_config, HIP events on the launching stream, median of
-several repetitions after warm-up), then the best one is timed again over a
-few tile orders (group_m); the winner goes into the tuning table that the
+several repetitions after warm-up) -- configurations with a split-K variant
+also with several split factors (misgemm_sgemm_split) when their tiles
+alone leave CUs idle -- then the best one is timed again over a few tile
+orders (group_m); the winner goes into the tuning table that the
 library reads (include/misgemm.h, misgemm_load_tuning).  Batched plans are
 tuned the same way over the configurations with a persistent variant, on
 the batch workload.  The paper fixes its block sizes at compile time; here
@@ -22,6 +24,7 @@ import sys
 import time
 
 GROUP_MS = [1, 4, 8, 16]
+SPLITS = [2, 4, 8, 16]
 
 
 def _time(fn, reps, warmup):
@@ -53,6 +56,9 @@ def default_keys():
                 keys.append((mode, ta, tb, s, s, s))
         for k in (128, 256, 512):
             keys.append((mode, "N", "N", 16384, 16384, k))
+        # skinny outputs with long K (the split-K regime)
+        for (m, n, k) in ((128, 512, 8192), (512, 512, 16384)):
+            keys.append((mode, "N", "N", m, n, k))
     return keys
 
 
@@ -60,7 +66,15 @@ def tune_gemm(keys, reps=5, warmup=2, log=print):
     import torch
     import paper_1608_05265_amd as mg
     dev = torch.device("cuda:0")
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
     results = []
+
+    def call(mode, ta, tb, m, n, k, A, ar, B, br, C, cid, gm, sp):
+        if sp == 1:
+            mg.sgemm_config(ta, tb, m, n, k, 1.0, A, ar, B, br, 0.5, C, m, mode, cid, gm)
+        else:
+            mg.sgemm_split(ta, tb, m, n, k, 1.0, A, ar, B, br, 0.5, C, m, mode, cid, gm, sp)
+
     for (mode, ta, tb, m, n, k) in keys:
         ar, ac = (k, m) if ta == "T" else (m, k)
         br, bc = (n, k) if tb == "T" else (k, n)
@@ -71,24 +85,29 @@ def tune_gemm(keys, reps=5, warmup=2, log=print):
         small = flops < 2e10
         r, w = (reps * 4, warmup * 2) if small else (reps, warmup)
         timings = {}
+        ids = {}
         for cfg in mg.configs(mode):
-            def fn(cid=cfg["id"]):
-                mg.sgemm_config(ta, tb, m, n, k, 1.0, A, ar, B, br, 0.5, C, m, mode, cid)
-            timings[cfg["name"]] = _time(fn, r, w)
-        best = min(timings, key=timings.get)
-        best_id = [c["id"] for c in mg.configs(mode) if c["name"] == best][0]
+            ids[cfg["name"]] = cfg["id"]
+            tiles = -(-m // cfg["bm"]) * -(-n // cfg["bn"])
+            splits = [1] + (SPLITS if cfg["splitk"] and tiles < 2 * cus else [])
+            for sp in splits:
+                def fn(cid=cfg["id"], sp=sp):
+                    call(mode, ta, tb, m, n, k, A, ar, B, br, C, cid, 0, sp)
+                timings[(cfg["name"], sp)] = _time(fn, r, w)
+        best, best_sp = min(timings, key=timings.get)
         orders = {}
         for gm in GROUP_MS:
             def fn(gm=gm):
-                mg.sgemm_config(ta, tb, m, n, k, 1.0, A, ar, B, br, 0.5, C, m, mode, best_id, gm)
+                call(mode, ta, tb, m, n, k, A, ar, B, br, C, ids[best], gm, best_sp)
             orders[gm] = _time(fn, r, w)
         best_gm = min(orders, key=orders.get)
         row = {"mode": mode, "ta": ta, "tb": tb, "m": m, "n": n, "k": k, "config": best,
-               "group_m": best_gm, "ms": orders[best_gm],
+               "group_m": best_gm, "splits": best_sp, "ms": orders[best_gm],
                "tflops": flops / (orders[best_gm] * 1e-3) / 1e12,
-               "all_ms": timings, "group_m_ms": orders}
-        log("mode %d %s%s %6d %6d %6d -> %-26s gm=%-2d %8.3f ms %7.1f TF/s"
-            % (mode, ta, tb, m, n, k, best, best_gm, row["ms"], row["tflops"]))
+               "all_ms": {"%s/s%d" % key: v for key, v in timings.items()},
+               "group_m_ms": orders}
+        log("mode %d %s%s %6d %6d %6d -> %-26s gm=%-2d splits=%-2d %8.3f ms %7.1f TF/s"
+            % (mode, ta, tb, m, n, k, best, best_gm, best_sp, row["ms"], row["tflops"]))
         results.append(row)
         del A, B, C
         torch.cuda.empty_cache()
@@ -131,10 +150,11 @@ def write_table(path, gemm_rows, batch):
     with open(path, "w") as f:
         f.write("misgemm-tuning 1\n")
         f.write("# written by paper_1608_05265_amd.autotune on %s\n" % time.strftime("%Y-%m-%d"))
-        f.write("# mode transa transb m n k config group_m   (best TFLOP/s)\n")
+        f.write("# mode transa transb m n k config group_m splits   (best TFLOP/s)\n")
         for r in gemm_rows:
-            f.write("%d %s %s %d %d %d %s %d\n" % (r["mode"], r["ta"], r["tb"], r["m"], r["n"],
-                                                   r["k"], r["config"], r["group_m"]))
+            f.write("%d %s %s %d %d %d %s %d %d\n" % (r["mode"], r["ta"], r["tb"], r["m"], r["n"],
+                                                      r["k"], r["config"], r["group_m"],
+                                                      r.get("splits", 1)))
             f.write("#   %.1f TFLOP/s\n" % r["tflops"])
         for mode, b in sorted(batch.items()):
             f.write("batch %d %s\n" % (mode, b["config"]))

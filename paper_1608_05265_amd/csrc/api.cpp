@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -75,6 +76,7 @@ struct TuneEntry {
     int64_t m, n, k;
     int config;
     int group_m;
+    int splits;  // 0: automatic, 1: whole K per workgroup, >= 2: split-K factor
 };
 std::vector<TuneEntry> g_tuning;
 int g_batch_config[2] = {-1, -1};  // per mode, from "batch" lines
@@ -90,7 +92,8 @@ int find_config(const char *name)
 
 // Nearest tuned entry (same mode and transposes, every size within a factor
 // 2, smallest summed log-distance); -1 when none.
-int tuned_config(int mode, int ta, int tb, int64_t m, int64_t n, int64_t k, int *group_m)
+int tuned_config(int mode, int ta, int tb, int64_t m, int64_t n, int64_t k, int *group_m,
+                 int *splits)
 {
     std::lock_guard<std::mutex> lock(g_tune_mutex);
     int best = -1;
@@ -102,7 +105,12 @@ int tuned_config(int mode, int ta, int tb, int64_t m, int64_t n, int64_t k, int 
         const double dk = fabs(log2((double)k / (double)e.k));
         if (dm > 1.0 || dn > 1.0 || dk > 1.0) continue;
         const double d = dm + dn + dk;
-        if (d < best_d) { best_d = d; best = e.config; *group_m = e.group_m; }
+        if (d < best_d) {
+            best_d = d;
+            best = e.config;
+            *group_m = e.group_m;
+            *splits = e.splits;
+        }
     }
     return best;
 }
@@ -131,12 +139,14 @@ int heuristic_config(int mode, int64_t m, int64_t n, int64_t k, int cus, bool al
 }
 
 int select_config(int mode, int ta, int tb, int64_t m, int64_t n, int64_t k, int cus,
-                  bool allow_packed, int *group_m)
+                  bool allow_packed, int *group_m, int *splits)
 {
     *group_m = GROUP_M_DEFAULT;
-    const int c = tuned_config(mode, ta, tb, m, n, k, group_m);
+    *splits = 0;
+    const int c = tuned_config(mode, ta, tb, m, n, k, group_m, splits);
     if (c >= 0 && (allow_packed || !configs()[c].desc.packed)) return c;
     *group_m = GROUP_M_DEFAULT;
+    *splits = 0;
     return heuristic_config(mode, m, n, k, cus, allow_packed);
 }
 
@@ -148,27 +158,33 @@ int64_t packed_bytes(int64_t m, int64_t n, int64_t k)
     return 2 * (pack_halves(m, k) + pack_halves(n, k)) + 512;
 }
 
-struct DeviceWorkspace {
+// Library-owned scratch, one set per (device, stream): calls on one stream
+// run in order, so they can share it; calls on different streams never do.
+struct StreamWorkspace {
     void *ptr = nullptr;
     int64_t bytes = 0;
     std::vector<void *> retired;  // outgrown buffers, kept for captured graphs
 };
-DeviceWorkspace g_ws[64];
+std::map<std::pair<int, void *>, StreamWorkspace> g_ws;
 std::mutex g_ws_mutex;
 
-// Library-owned workspace of at least `bytes` on the current device, or
-// nullptr when it would have to grow while `s` is capturing or the
-// allocation fails.
+bool capturing(hipStream_t s)
+{
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone;
+}
+
+// Library-owned workspace of at least `bytes` for the current device and
+// stream `s`, or nullptr when it would have to grow while `s` is capturing or
+// the allocation fails.
 void *library_workspace(int64_t bytes, hipStream_t s)
 {
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
     std::lock_guard<std::mutex> lock(g_ws_mutex);
-    DeviceWorkspace &w = g_ws[dev];
+    StreamWorkspace &w = g_ws[{dev, (void *)s}];
     if (w.bytes >= bytes) return w.ptr;
-    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone)
-        return nullptr;
+    if (capturing(s)) return nullptr;
     const int64_t want = std::max<int64_t>(bytes, w.bytes + w.bytes / 2);
     void *p = nullptr;
     if (hipMalloc(&p, (size_t)want) != hipSuccess) {
@@ -239,16 +255,46 @@ GemmArgs make_args(int64_t m, int64_t n, int64_t k, float alpha, const float *A,
     g.vec_a = aligned16(A) && lda % 4 == 0;
     g.vec_b = aligned16(B) && ldb % 4 == 0;
     g.vec_c = aligned16(C) && ldc % 4 == 0;
+    g.part = nullptr;
+    g.tile = 0;
+    g.split = 0;
+    g.splits = 1;
     return g;
 }
 
 // Workspace policy of one call.
 enum WsPolicy { WS_LIBRARY, WS_CALLER, WS_NONE };
 
+// Split-K factor for a non-packed configuration when neither the caller nor
+// the tuning table fixed one: only when the tiles leave CUs idle, enough
+// splits for about two workgroups per CU, each split at least eight K blocks
+// (shorter ranges lose more to the second launch and the partial traffic
+// than they gain), at most 16.
+int auto_splits(const ConfigEntry &e, int64_t tiles, int64_t k, int cus)
+{
+    if (e.splitk[0][0] == nullptr || tiles >= cus) return 1;
+    const int64_t kt = (k + e.desc.bk - 1) / e.desc.bk;
+    int64_t s = (2 * (int64_t)cus + tiles - 1) / tiles;
+    s = std::min<int64_t>(s, std::min<int64_t>(kt / 8, 16));
+    return s < 2 ? 1 : (int)s;
+}
+
+// Splits actually launched for a request: every split gets a non-empty,
+// whole-block K range.
+int effective_splits(int64_t k, int bk, int req)
+{
+    const int64_t kt = (k + bk - 1) / bk;
+    if (req <= 1 || kt <= 1) return 1;
+    const int64_t per = (kt + req - 1) / req;
+    return (int)((kt + per - 1) / per);
+}
+
+// splits_req: 0 = automatic (tuning table, then auto_splits), >= 1 = forced.
 int run_sgemm(char transa, char transb, int64_t m, int64_t n, int64_t k, float alpha,
               const float *A, int64_t lda, const float *B, int64_t ldb, float beta, float *C,
               int64_t ldc, int mode, int config_id, int group_m, void *stream,
-              WsPolicy policy = WS_LIBRARY, void *workspace = nullptr, int64_t ws_bytes = 0)
+              WsPolicy policy = WS_LIBRARY, void *workspace = nullptr, int64_t ws_bytes = 0,
+              int splits_req = 0)
 {
     int rc = validate(transa, transb, m, n, k, alpha, A, lda, B, ldb, C, ldc, mode);
     if (rc != 0) return rc;
@@ -268,8 +314,11 @@ int run_sgemm(char transa, char transb, int64_t m, int64_t n, int64_t k, float a
     const bool packable = mode == MISGEMM_BF16X3 && policy != WS_NONE &&
                           pack_kblocks(k) <= 65535;
     int cfg = config_id;
-    if (cfg < 0) cfg = select_config(mode, ta, tb, m, n, k, dev->cus, packable, &gm);
+    int splits = splits_req;
+    int tuned_splits = 0;
+    if (cfg < 0) cfg = select_config(mode, ta, tb, m, n, k, dev->cus, packable, &gm, &tuned_splits);
     if (cfg < 0) return MISGEMM_E_BAD_CONFIG;
+    if (splits == 0) splits = tuned_splits;
     void *ws = nullptr;
     if (table[cfg].desc.packed) {
         if (pack_kblocks(k) > 65535) return MISGEMM_E_TOO_LARGE;
@@ -281,14 +330,31 @@ int run_sgemm(char transa, char transb, int64_t m, int64_t n, int64_t k, float a
             // no workspace (capturing, or none given): a non-packed config
             cfg = heuristic_config(mode, m, n, k, dev->cus, false);
             gm = group_m > 0 ? group_m : GROUP_M_DEFAULT;
+            splits = splits_req;
         }
     }
-    const misgemm_config_desc &d = table[cfg].desc;
+    const ConfigEntry &e = table[cfg];
+    const misgemm_config_desc &d = e.desc;
     const int64_t tiles = ((m + d.bm - 1) / d.bm) * ((n + d.bn - 1) / d.bn);
     if (tiles > INT32_MAX) return MISGEMM_E_TOO_LARGE;
-    const GemmArgs g = make_args(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
-    if (d.packed) return (int)launch_packed_path(table[cfg], ta, tb, g, ws, gm, s);
-    return (int)table[cfg].launch[ta][tb](g, gm, s);
+    GemmArgs g = make_args(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+    if (d.packed) return (int)launch_packed_path(e, ta, tb, g, ws, gm, s);
+    const bool forced = splits_req >= 1;
+    if (splits == 0) splits = policy == WS_LIBRARY ? auto_splits(e, tiles, k, dev->cus) : 1;
+    splits = effective_splits(k, d.bk, splits);
+    if (splits > 1) {
+        if (e.splitk[0][0] == nullptr) return MISGEMM_E_BAD_CONFIG;
+        float *part = nullptr;
+        if (policy == WS_LIBRARY)
+            part = (float *)library_workspace(splits * tiles * d.bm * d.bn * 4, s);
+        if (part != nullptr) {
+            g.part = part;
+            g.splits = splits;
+            return (int)e.splitk[ta][tb](g, gm, s);
+        }
+        if (forced) return MISGEMM_E_CAPTURING;
+    }
+    return (int)e.launch[ta][tb](g, gm, s);
 }
 
 }  // namespace
@@ -327,7 +393,30 @@ int misgemm_sgemm_config(char transa, char transb, int64_t m, int64_t n, int64_t
     if (config_id < 0) return -15;
     if (group_m < 0 || group_m > 4096) return -16;
     return run_sgemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, mode,
-                     config_id, group_m, stream);
+                     config_id, group_m, stream, WS_LIBRARY, nullptr, 0, 1);
+}
+
+int misgemm_sgemm_split(char transa, char transb, int64_t m, int64_t n, int64_t k, float alpha,
+                        const float *A, int64_t lda, const float *B, int64_t ldb, float beta,
+                        float *C, int64_t ldc, int mode, int config_id, int group_m, int splits,
+                        void *stream)
+{
+    if (group_m < 0 || group_m > 4096) return -16;
+    if (splits < 1 || splits > 64) return -17;
+    if (config_id < 0 && splits > 1) {
+        // the split-capable configuration of the mode with the smallest tile
+        const auto &t = configs();
+        int64_t best = INT64_MAX;
+        for (size_t i = 0; i < t.size(); ++i) {
+            const int64_t area = (int64_t)t[i].desc.bm * t[i].desc.bn;
+            if (t[i].desc.mode == mode && t[i].splitk[0][0] && area < best) {
+                best = area;
+                config_id = (int)i;
+            }
+        }
+    }
+    return run_sgemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, mode,
+                     config_id, group_m, stream, WS_LIBRARY, nullptr, 0, splits);
 }
 
 int64_t misgemm_workspace_size(char transa, char transb, int64_t m, int64_t n, int64_t k,
@@ -364,15 +453,16 @@ int misgemm_sgemm_ws(char transa, char transb, int64_t m, int64_t n, int64_t k, 
 int misgemm_release_workspace(void)
 {
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return MISGEMM_E_NO_DEVICE;
+    if (hipGetDevice(&dev) != hipSuccess) return MISGEMM_E_NO_DEVICE;
     hipError_t e = hipDeviceSynchronize();
     std::lock_guard<std::mutex> lock(g_ws_mutex);
-    DeviceWorkspace &w = g_ws[dev];
-    if (w.ptr) (void)hipFree(w.ptr);
-    for (void *p : w.retired) (void)hipFree(p);
-    w.ptr = nullptr;
-    w.bytes = 0;
-    w.retired.clear();
+    for (auto it = g_ws.begin(); it != g_ws.end();) {
+        if (it->first.first != dev) { ++it; continue; }
+        StreamWorkspace &w = it->second;
+        if (w.ptr) (void)hipFree(w.ptr);
+        for (void *p : w.retired) (void)hipFree(p);
+        it = g_ws.erase(it);
+    }
     return (int)e;
 }
 
@@ -383,6 +473,7 @@ int misgemm_config_info(int id, misgemm_config_desc *out)
     if (id < 0 || id >= (int)configs().size()) return -1;
     if (out == nullptr) return -2;
     *out = configs()[id].desc;
+    out->splitk = configs()[id].splitk[0][0] != nullptr;
     return 0;
 }
 
@@ -398,8 +489,8 @@ int misgemm_select_config(char transa, char transb, int64_t m, int64_t n, int64_
     DeviceInfo *dev = nullptr;
     int cus = 256;
     if (current_device(&dev) == 0) cus = dev->cus;
-    int gm = 0;
-    return select_config(mode, ta, tb, m, n, k, cus, mode == MISGEMM_BF16X3, &gm);
+    int gm = 0, splits = 0;
+    return select_config(mode, ta, tb, m, n, k, cus, mode == MISGEMM_BF16X3, &gm, &splits);
 }
 
 int misgemm_load_tuning(const char *path)
@@ -436,17 +527,21 @@ int misgemm_load_tuning(const char *path)
             }
             char ta, tb;
             long long m, n, k;
-            int gm = GROUP_M_DEFAULT;
-            const int got = sscanf(line, "%d %c %c %lld %lld %lld %63s %d", &mode, &ta, &tb, &m,
-                                   &n, &k, name, &gm);
+            int gm = GROUP_M_DEFAULT, sp = 0;
+            const int got = sscanf(line, "%d %c %c %lld %lld %lld %63s %d %d", &mode, &ta, &tb,
+                                   &m, &n, &k, name, &gm, &sp);
             if (got < 7 || m <= 0 || n <= 0 || k <= 0 || trans_flag(ta) < 0 ||
-                trans_flag(tb) < 0 || gm <= 0 || gm > 4096) {
+                trans_flag(tb) < 0 || gm <= 0 || gm > 4096 || sp < 0 || sp > 64) {
                 rc = MISGEMM_E_TUNING_FILE;
                 break;
             }
             const int id = find_config(name);
-            if (id < 0 || configs()[id].desc.mode != mode) { rc = MISGEMM_E_TUNING_FILE; break; }
-            entries.push_back({mode, trans_flag(ta), trans_flag(tb), m, n, k, id, gm});
+            if (id < 0 || configs()[id].desc.mode != mode ||
+                (sp > 1 && configs()[id].splitk[0][0] == nullptr)) {
+                rc = MISGEMM_E_TUNING_FILE;
+                break;
+            }
+            entries.push_back({mode, trans_flag(ta), trans_flag(tb), m, n, k, id, gm, sp});
         }
         fclose(f);
         if (rc == 0 && !header) rc = MISGEMM_E_TUNING_FILE;
@@ -707,6 +802,6 @@ const char *misgemm_status_string(int status)
     return buf;
 }
 
-const char *misgemm_version(void) { return "misgemm 0.1 (gfx950)"; }
+const char *misgemm_version(void) { return "misgemm 0.2 (gfx950)"; }
 
 }  // extern "C"

@@ -37,14 +37,22 @@ struct GemmArgs {
     int64_t lda, ldb, ldc;
     float alpha, beta;
     int vec_a, vec_b, vec_c;  // 16-byte vector access legal (aligned base, ld % 4 == 0)
+    // Split-K (read only by the split kernels): this workgroup computes the
+    // K range of split `split` of `splits` for tile `tile`; its partial sums
+    // go to `part`.
+    float *part;
+    int64_t tile;
+    int split, splits;
 };
 
 // ---------------------------------------------------------------------------
 // Tile shape: BM x BN per workgroup, BK per K block, WM x WN per wave.
 // ---------------------------------------------------------------------------
-template <int BM_, int BN_, int BK_, int WM_, int WN_>
+// OCC_: waves per SIMD the register allocation must leave room for
+// (a launch bound; 8-wave tiles get two per SIMD by construction).
+template <int BM_, int BN_, int BK_, int WM_, int WN_, int OCC_ = 1>
 struct Shape {
-    static constexpr int BM = BM_, BN = BN_, BK = BK_, WM = WM_, WN = WN_;
+    static constexpr int BM = BM_, BN = BN_, BK = BK_, WM = WM_, WN = WN_, OCC = OCC_;
     static constexpr int NWM = BM / WM, NWN = BN / WN, NW = NWM * NWN, NT = 64 * NW;
     static constexpr int RM = WM / 32, RN = WN / 32;  // 32x32 MFMA blocks per wave
     static_assert(BM % WM == 0 && BN % WN == 0, "wave tiles must divide the tile");
@@ -301,6 +309,46 @@ __device__ __forceinline__ void epilogue(const GemmArgs &g, const floatx16 (&acc
 }
 
 // ---------------------------------------------------------------------------
+// End of a tile.  A whole-K tile applies alpha/beta and stores.  A split-K
+// tile (SPLIT) stores its raw partial accumulator instead; a second kernel
+// (splitk_reduce) adds the partials of all splits in split order and runs
+// the epilogue, so the result does not depend on the order in which the
+// splits ran.  Partial layout: for split s of tile t, float4 group q of
+// thread x is at part[((t * splits + s) * Q + q) * NT + x] (Q = RM*RN*4
+// groups per thread), so each store instruction of a wave writes 1 KB
+// contiguously.
+// ---------------------------------------------------------------------------
+template <int RM, int RN>
+__device__ __forceinline__ int64_t partial_index(int64_t tile, int splits, int split, int q,
+                                                 int tid, int nt)
+{
+    return ((tile * splits + split) * (int64_t)(RM * RN * 4) + q) * nt + tid;
+}
+
+template <bool SPLIT, int RM, int RN>
+__device__ __forceinline__ void finish(const GemmArgs &g, const floatx16 (&acc)[RM][RN],
+                                       int64_t row0, int64_t col0, int tid, int nt)
+{
+    if constexpr (SPLIT) {
+        floatx4 *const part = reinterpret_cast<floatx4 *>(g.part);
+#pragma unroll
+        for (int i = 0; i < RM; ++i)
+#pragma unroll
+            for (int j = 0; j < RN; ++j)
+#pragma unroll
+                for (int q4 = 0; q4 < 4; ++q4) {
+                    floatx4 v;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) v[e] = acc[i][j][q4 * 4 + e];
+                    part[partial_index<RM, RN>(g.tile, g.splits, g.split, (i * RN + j) * 4 + q4,
+                                               tid, nt)] = v;
+                }
+    } else {
+        epilogue<RM, RN>(g, acc, row0, col0, tid & 63);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // The tile body: stage -> multiply -> epilogue for tile (m0, n0).
 // ---------------------------------------------------------------------------
 template <class SH, bool TA, bool TB>
@@ -313,16 +361,17 @@ struct F32Tile {
 
     // Interior tiles whose K range is a whole number of blocks take the
     // unmasked load path; every other tile masks its loads.
+    template <bool SPLIT = false>
     __device__ __forceinline__ static void run(const GemmArgs &g, int64_t m0, int64_t n0,
                                                char *smem)
     {
         const bool fast = m0 + SH::BM <= g.m && n0 + SH::BN <= g.n && g.k % SH::BK == 0 &&
                           (g.vec_a || !SA::NEEDS_VEC) && (g.vec_b || !SB::NEEDS_VEC);
-        if (fast) run_impl<true>(g, m0, n0, smem);
-        else run_impl<false>(g, m0, n0, smem);
+        if (fast) run_impl<true, SPLIT>(g, m0, n0, smem);
+        else run_impl<false, SPLIT>(g, m0, n0, smem);
     }
 
-    template <bool FAST>
+    template <bool FAST, bool SPLIT>
     __device__ __forceinline__ static void run_impl(const GemmArgs &g, int64_t m0, int64_t n0,
                                                     char *smem)
     {
@@ -381,7 +430,7 @@ struct F32Tile {
             }
             __syncthreads();
         }
-        epilogue<SH::RM, SH::RN>(g, acc, m0 + wm * SH::WM, n0 + wn * SH::WN, lane);
+        finish<SPLIT, SH::RM, SH::RN>(g, acc, m0 + wm * SH::WM, n0 + wn * SH::WN, tid, NT);
     }
 };
 
@@ -446,16 +495,17 @@ struct F32PTile {
 
     // Interior tiles whose K range is a whole number of blocks take the
     // unmasked load path; every other tile masks its loads.
+    template <bool SPLIT = false>
     __device__ __forceinline__ static void run(const GemmArgs &g, int64_t m0, int64_t n0,
                                                char *smem)
     {
         const bool fast = m0 + SH::BM <= g.m && n0 + SH::BN <= g.n && g.k % SH::BK == 0 &&
                           (g.vec_a || !SA::NEEDS_VEC) && (g.vec_b || !SB::NEEDS_VEC);
-        if (fast) run_impl<true>(g, m0, n0, smem);
-        else run_impl<false>(g, m0, n0, smem);
+        if (fast) run_impl<true, SPLIT>(g, m0, n0, smem);
+        else run_impl<false, SPLIT>(g, m0, n0, smem);
     }
 
-    template <bool FAST>
+    template <bool FAST, bool SPLIT>
     __device__ __forceinline__ static void run_impl(const GemmArgs &g, int64_t m0, int64_t n0,
                                                     char *smem)
     {
@@ -495,7 +545,7 @@ struct F32PTile {
             body(acc, cur, nxt, sa, sb, tid, wm, wn, half, l32);
             __syncthreads();
         }
-        epilogue<RM, RN>(g, acc, m0 + wm * SH::WM, n0 + wn * SH::WN, lane);
+        finish<SPLIT, RM, RN>(g, acc, m0 + wm * SH::WM, n0 + wn * SH::WN, tid, NT);
     }
 };
 
@@ -510,16 +560,17 @@ struct X3Tile {
 
     // Interior tiles whose K range is a whole number of blocks take the
     // unmasked load path; every other tile masks its loads.
+    template <bool SPLIT = false>
     __device__ __forceinline__ static void run(const GemmArgs &g, int64_t m0, int64_t n0,
                                                char *smem)
     {
         const bool fast = m0 + SH::BM <= g.m && n0 + SH::BN <= g.n && g.k % SH::BK == 0 &&
                           (g.vec_a || !SA::NEEDS_VEC) && (g.vec_b || !SB::NEEDS_VEC);
-        if (fast) run_impl<true>(g, m0, n0, smem);
-        else run_impl<false>(g, m0, n0, smem);
+        if (fast) run_impl<true, SPLIT>(g, m0, n0, smem);
+        else run_impl<false, SPLIT>(g, m0, n0, smem);
     }
 
-    template <bool FAST>
+    template <bool FAST, bool SPLIT>
     __device__ __forceinline__ static void run_impl(const GemmArgs &g, int64_t m0, int64_t n0,
                                                     char *smem)
     {
@@ -608,7 +659,7 @@ struct X3Tile {
                 for (int j = 0; j < SH::RN; ++j)
                     acc[i][j] += lo[ACC2 ? i : 0][ACC2 ? j : 0];
         }
-        epilogue<SH::RM, SH::RN>(g, acc, m0 + wm * SH::WM, n0 + wn * SH::WN, lane);
+        finish<SPLIT, SH::RM, SH::RN>(g, acc, m0 + wm * SH::WM, n0 + wn * SH::WN, tid, NT);
     }
 };
 
@@ -767,16 +818,17 @@ struct X3PTile {
 
     // Interior tiles whose K range is a whole number of blocks take the
     // unmasked load path; every other tile masks its loads.
+    template <bool SPLIT = false>
     __device__ __forceinline__ static void run(const GemmArgs &g, int64_t m0, int64_t n0,
                                                char *smem)
     {
         const bool fast = m0 + SH::BM <= g.m && n0 + SH::BN <= g.n && g.k % SH::BK == 0 &&
                           (g.vec_a || !SA::NEEDS_VEC) && (g.vec_b || !SB::NEEDS_VEC);
-        if (fast) run_impl<true>(g, m0, n0, smem);
-        else run_impl<false>(g, m0, n0, smem);
+        if (fast) run_impl<true, SPLIT>(g, m0, n0, smem);
+        else run_impl<false, SPLIT>(g, m0, n0, smem);
     }
 
-    template <bool FAST>
+    template <bool FAST, bool SPLIT>
     __device__ __forceinline__ static void run_impl(const GemmArgs &g, int64_t m0, int64_t n0,
                                                     char *smem)
     {
@@ -817,7 +869,7 @@ struct X3PTile {
             body<true>(acc, cur, nxt, sa, sb, tid, wm, wn, half, l32);
             __syncthreads();
         }
-        epilogue<RM, RN>(g, acc, m0 + wm * SH::WM, n0 + wn * SH::WN, lane);
+        finish<SPLIT, RM, RN>(g, acc, m0 + wm * SH::WM, n0 + wn * SH::WN, tid, NT);
     }
 };
 

@@ -46,6 +46,7 @@ typedef hipError_t (*packed_launch_fn)(const PackedArgs &p, int group_m, hipStre
 struct ConfigEntry {
     misgemm_config_desc desc;
     launch_fn launch[2][2];    // [transa][transb]; NULL for packed configs
+    launch_fn splitk[2][2];    // split-K variant (g.splits > 1 set); NULL when not compiled
     batch_launch_fn batch;     // NULL when no persistent variant is compiled
     occupancy_fn batch_occupancy;
     packed_launch_fn packed;   // tile kernel on packed panels (packed configs only)
@@ -55,7 +56,7 @@ struct ConfigEntry {
 constexpr int GROUP_M_DEFAULT = 8;
 
 template <class TILE, class SH>
-__global__ __launch_bounds__(SH::NT, 1) void sgemm_kernel(GemmArgs g, int64_t tiles_m,
+__global__ __launch_bounds__(SH::NT, SH::OCC) void sgemm_kernel(GemmArgs g, int64_t tiles_m,
                                                           int64_t tiles_n, int group_m)
 {
     __shared__ __attribute__((aligned(16))) char smem[TILE::LDS_BYTES];
@@ -74,6 +75,86 @@ hipError_t launch_tile_kernel(const GemmArgs &g, int group_m, hipStream_t s)
     return hipGetLastError();
 }
 
+// Split-K, first kernel: workgroup b (after the XCD remap) computes split
+// b % splits of tile b / splits over the K range [s*kblk, min(k, (s+1)*kblk)),
+// kblk a whole number of BK blocks, and stores its raw partial tile.
+__host__ __device__ inline int64_t splitk_kblk(int64_t k, int bk, int splits)
+{
+    const int64_t kt = (k + bk - 1) / bk;
+    return (kt + splits - 1) / splits * bk;
+}
+
+template <class TILE, class SH, bool TA, bool TB>
+__global__ __launch_bounds__(SH::NT, SH::OCC) void splitk_kernel(GemmArgs g, int64_t tiles_m,
+                                                                 int64_t tiles_n, int group_m)
+{
+    __shared__ __attribute__((aligned(16))) char smem[TILE::LDS_BYTES];
+    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t tile = t / g.splits;
+    const int s = (int)(t % g.splits);
+    int64_t tm, tn;
+    tile_coords(tile, tiles_m, tiles_n, group_m, tm, tn);
+    const int64_t kblk = splitk_kblk(g.k, SH::BK, g.splits);
+    const int64_t k0 = s * kblk;
+    GemmArgs gs = g;
+    gs.k = g.k - k0 < kblk ? g.k - k0 : kblk;
+    gs.A = TA ? g.A + k0 : g.A + k0 * g.lda;   // op(A)(i, k0 + p)
+    gs.B = TB ? g.B + k0 * g.ldb : g.B + k0;   // op(B)(k0 + p, j)
+    gs.tile = tile;
+    gs.split = s;
+    TILE::template run<true>(gs, tm * SH::BM, tn * SH::BN, smem);
+}
+
+// Split-K, second kernel: one workgroup per tile, threads laid out as in the
+// tile kernel (so each thread owns the same accumulator entries), adds the
+// partials of splits 0, 1, ... in that order and applies alpha/beta.
+template <class SH>
+__global__ __launch_bounds__(SH::NT) void splitk_reduce_kernel(GemmArgs g, int64_t tiles_m,
+                                                               int64_t tiles_n, int group_m)
+{
+    constexpr int RM = SH::RM, RN = SH::RN;
+    const int64_t tile = blockIdx.x;
+    int64_t tm, tn;
+    tile_coords(tile, tiles_m, tiles_n, group_m, tm, tn);
+    const int tid = threadIdx.x, wave = tid >> 6;
+    const int wm = wave % SH::NWM, wn = wave / SH::NWM;
+    const floatx4 *part = reinterpret_cast<const floatx4 *>(g.part);
+    floatx16 acc[RM][RN];
+#pragma unroll
+    for (int i = 0; i < RM; ++i)
+#pragma unroll
+        for (int j = 0; j < RN; ++j)
+#pragma unroll
+            for (int q4 = 0; q4 < 4; ++q4) {
+                const int q = (i * RN + j) * 4 + q4;
+                floatx4 sum = part[partial_index<RM, RN>(tile, g.splits, 0, q, tid, SH::NT)];
+                for (int s = 1; s < g.splits; ++s) {
+                    const floatx4 v = part[partial_index<RM, RN>(tile, g.splits, s, q, tid, SH::NT)];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) sum[e] += v[e];
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[i][j][q4 * 4 + e] = sum[e];
+            }
+    epilogue<RM, RN>(g, acc, tm * SH::BM + wm * SH::WM, tn * SH::BN + wn * SH::WN, tid & 63);
+}
+
+// g.splits >= 2 with every split's K range non-empty (the host sets splits =
+// ceil(ktiles / ceil(ktiles / requested))), g.part sized for splits * tiles
+// partial tiles.  Two launches on stream s.
+template <class TILE, class SH, bool TA, bool TB>
+hipError_t launch_splitk_kernel(const GemmArgs &g, int group_m, hipStream_t s)
+{
+    const int64_t tm = (g.m + SH::BM - 1) / SH::BM, tn = (g.n + SH::BN - 1) / SH::BN;
+    hipLaunchKernelGGL((splitk_kernel<TILE, SH, TA, TB>), dim3((unsigned)(tm * tn * g.splits)),
+                       dim3(SH::NT), 0, s, g, tm, tn, group_m);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((splitk_reduce_kernel<SH>), dim3((unsigned)(tm * tn)), dim3(SH::NT), 0, s,
+                       g, tm, tn, group_m);
+    return hipGetLastError();
+}
+
 template <int A, int B>
 struct MaxI { static constexpr int value = A > B ? A : B; };
 
@@ -81,7 +162,7 @@ struct MaxI { static constexpr int value = A > B ? A : B; };
 // takes tiles w, w + grid, w + 2*grid, ... of a list sorted by decreasing
 // work, so the longest tiles start first.
 template <template <class, bool, bool> class TILE, class SH>
-__global__ __launch_bounds__(SH::NT, 1) void batch_kernel(const ProbDev *__restrict__ probs,
+__global__ __launch_bounds__(SH::NT, SH::OCC) void batch_kernel(const ProbDev *__restrict__ probs,
                                                           const TileDev *__restrict__ tiles,
                                                           BatchSplit split)
 {

@@ -12,7 +12,7 @@ using F32 = F32Tile<SH, TA, TB>;
 template <class SH, bool TA, bool TB>
 using F32P = F32PTile<SH, TA, TB>;
 
-template <template <class, bool, bool> class T, class SH, bool BATCHED>
+template <template <class, bool, bool> class T, class SH, bool BATCHED, bool SPLITK = false>
 ConfigEntry make_f32(const char *name)
 {
     ConfigEntry e;
@@ -34,6 +34,12 @@ ConfigEntry make_f32(const char *name)
         e.batch = launch_batch_kernel<T, SH>;
         e.batch_occupancy = batch_occupancy<T, SH>;
     }
+    if constexpr (SPLITK) {
+        e.splitk[0][0] = launch_splitk_kernel<T<SH, false, false>, SH, false, false>;
+        e.splitk[0][1] = launch_splitk_kernel<T<SH, false, true>, SH, false, true>;
+        e.splitk[1][0] = launch_splitk_kernel<T<SH, true, false>, SH, true, false>;
+        e.splitk[1][1] = launch_splitk_kernel<T<SH, true, true>, SH, true, true>;
+    }
     return e;
 }
 
@@ -43,12 +49,13 @@ void register_f32(std::vector<ConfigEntry> &out)
 {
     out.push_back(make_f32<F32P, Shape<256, 256, 16, 128, 64>, false>("fp32p_256x256x16_w128x64"));
     out.push_back(make_f32<F32P, Shape<256, 256, 32, 128, 64>, false>("fp32p_256x256x32_w128x64"));
-    out.push_back(make_f32<F32P, Shape<128, 128, 16, 64, 64>, true>("fp32p_128x128x16_w64x64"));
+    out.push_back(make_f32<F32P, Shape<256, 128, 16, 128, 64, 2>, false>("fp32p_256x128x16_w128x64"));
+    out.push_back(make_f32<F32P, Shape<128, 128, 16, 64, 64>, true, true>("fp32p_128x128x16_w64x64"));
     out.push_back(make_f32<F32P, Shape<128, 128, 32, 64, 64>, true>("fp32p_128x128x32_w64x64"));
-    out.push_back(make_f32<F32P, Shape<64, 64, 32, 32, 32>, true>("fp32p_64x64x32_w32x32"));
-    out.push_back(make_f32<F32, Shape<128, 128, 16, 64, 64>, true>("fp32_128x128x16_w64x64"));
+    out.push_back(make_f32<F32P, Shape<64, 64, 32, 32, 32>, true, true>("fp32p_64x64x32_w32x32"));
+    out.push_back(make_f32<F32, Shape<128, 128, 16, 64, 64>, true, true>("fp32_128x128x16_w64x64"));
     out.push_back(make_f32<F32, Shape<128, 64, 16, 64, 32>, true>("fp32_128x64x16_w64x32"));
-    out.push_back(make_f32<F32, Shape<64, 64, 16, 32, 32>, true>("fp32_64x64x16_w32x32"));
+    out.push_back(make_f32<F32, Shape<64, 64, 16, 32, 32>, true, true>("fp32_64x64x16_w32x32"));
 }
 
 }  // namespace misgemm

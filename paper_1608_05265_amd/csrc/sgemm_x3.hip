@@ -22,7 +22,7 @@ using X3P13 = X3PTile<SH, TA, TB, 1, 3>;
 template <class SH, bool TA, bool TB>
 using X3F13 = X3PTile<SH, TA, TB, 1, 3, true>;
 
-template <template <class, bool, bool> class T, class SH, bool BATCHED>
+template <template <class, bool, bool> class T, class SH, bool BATCHED, bool SPLITK = false>
 ConfigEntry make_x3(const char *name)
 {
     ConfigEntry e;
@@ -44,6 +44,12 @@ ConfigEntry make_x3(const char *name)
         e.batch = launch_batch_kernel<T, SH>;
         e.batch_occupancy = batch_occupancy<T, SH>;
     }
+    if constexpr (SPLITK) {
+        e.splitk[0][0] = launch_splitk_kernel<T<SH, false, false>, SH, false, false>;
+        e.splitk[0][1] = launch_splitk_kernel<T<SH, false, true>, SH, false, true>;
+        e.splitk[1][0] = launch_splitk_kernel<T<SH, true, false>, SH, true, false>;
+        e.splitk[1][1] = launch_splitk_kernel<T<SH, true, true>, SH, true, true>;
+    }
     return e;
 }
 
@@ -55,10 +61,10 @@ void register_x3(std::vector<ConfigEntry> &out)
     out.push_back(make_x3<X3F13, Shape<256, 256, 16, 128, 64>, false>("x3f_256x256x16_w128x64"));
     out.push_back(make_x3<X3F13, Shape<256, 256, 16, 64, 128>, false>("x3f_256x256x16_w64x128"));
     out.push_back(make_x3<X3F13, Shape<256, 256, 16, 128, 128>, false>("x3f_256x256x16_w128x128"));
-    out.push_back(make_x3<X3P13, Shape<128, 128, 16, 64, 64>, true>("x3p_128x128x16_w64x64"));
+    out.push_back(make_x3<X3P13, Shape<128, 128, 16, 64, 64>, true, true>("x3p_128x128x16_w64x64"));
     out.push_back(make_x3<X3S, Shape<128, 128, 32, 64, 64>, true>("x3_128x128x32_w64x64"));
-    out.push_back(make_x3<X3D, Shape<128, 128, 32, 64, 64>, true>("x3d_128x128x32_w64x64"));
-    out.push_back(make_x3<X3S, Shape<64, 64, 32, 32, 32>, true>("x3_64x64x32_w32x32"));
+    out.push_back(make_x3<X3D, Shape<128, 128, 32, 64, 64>, true, true>("x3d_128x128x32_w64x64"));
+    out.push_back(make_x3<X3S, Shape<64, 64, 32, 32, 32>, true, true>("x3_64x64x32_w32x32"));
 }
 
 }  // namespace misgemm

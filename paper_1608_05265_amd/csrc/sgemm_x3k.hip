@@ -7,7 +7,7 @@
 namespace misgemm {
 
 template <class SH>
-__global__ __launch_bounds__(SH::NT, 1) void packed_kernel(PackedArgs p, int64_t tiles_m,
+__global__ __launch_bounds__(SH::NT, SH::OCC) void packed_kernel(PackedArgs p, int64_t tiles_m,
                                                            int64_t tiles_n, int group_m)
 {
     __shared__ __attribute__((aligned(16))) char smem[X3KTile<SH>::LDS_BYTES];
@@ -27,7 +27,7 @@ hipError_t launch_packed(const PackedArgs &p, int group_m, hipStream_t s)
 }
 
 template <class SH>
-__global__ __launch_bounds__(SH::NT, 1) void packed_direct_kernel(PackedArgs p, int64_t tiles_m,
+__global__ __launch_bounds__(SH::NT, SH::OCC) void packed_direct_kernel(PackedArgs p, int64_t tiles_m,
                                                                   int64_t tiles_n, int group_m)
 {
     constexpr int SB = X3DTile<SH>::STAGE_BYTES;

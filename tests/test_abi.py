@@ -53,6 +53,10 @@ def test_configs_and_strings(mg):
     assert "position 8" in mg.status_string(-8)
     assert "tuning" in mg.status_string(1003)
     assert "gfx950" in mg.version()
+    # split-K variants exist for the small tiles of both forms, not the 256x256 ones
+    for mode in (0, 1):
+        split = [c for c in mg.configs(mode) if c["splitk"]]
+        assert split and all(c["bm"] * c["bn"] <= 128 * 128 and not c["packed"] for c in split)
 
 
 @pytest.mark.parametrize("case,expected", [
@@ -85,6 +89,14 @@ def test_quick_returns_need_no_device(mg):
                                     999, 0, None) == -15
     assert lib.misgemm_sgemm_config(b"N", b"N", 5, 5, 5, 1.0, 0x10, 5, 0x10, 5, 0.0, 0x10, 5, 0,
                                     0, -1, None) == -16
+    # split-K factor and tile order are checked before any HIP call
+    for splits in (0, -1, 65):
+        assert lib.misgemm_sgemm_split(b"N", b"N", 5, 5, 5, 1.0, 0x10, 5, 0x10, 5, 0.0, 0x10, 5,
+                                       0, -1, 0, splits, None) == -17
+    assert lib.misgemm_sgemm_split(b"N", b"N", 5, 5, 5, 1.0, 0x10, 5, 0x10, 5, 0.0, 0x10, 5, 0,
+                                   -1, -1, 2, None) == -16
+    assert lib.misgemm_sgemm_split(b"N", b"N", 0, 5, 5, 1.0, None, 1, None, 5, 0.0, None, 1, 0,
+                                   -1, 0, 4, None) == 0
     assert lib.misgemm_bf16x3_split(None, 0, None, None) == 0
     assert lib.misgemm_bf16x3_split(None, 3, None, None) == -1
     assert lib.misgemm_batch_launch(None, None) == 1005
@@ -99,13 +111,23 @@ def test_tuning_table_parsing(mg, tmp_path):
                     "1 T N 1000 2000 300 %s\n" % (f32[-1]["name"], x3[-1]["name"]))
     mg.load_tuning(str(good))
     assert mg.select_config("N", "T", 4096, 4096, 4096, 0) == f32[-1]["id"]
+    split = [c for c in f32 if c["splitk"]][0]
+    nosplit = [c for c in f32 if not c["splitk"]][0]
+    withsplit = tmp_path / "split.txt"
+    withsplit.write_text("misgemm-tuning 1\n0 N N 1024 1024 1024 %s 8 4\n"
+                         "0 T N 1024 1024 1024 %s 8 1\n" % (split["name"], nosplit["name"]))
+    mg.load_tuning(str(withsplit))
+    assert mg.select_config("N", "N", 1024, 1024, 1024, 0) == split["id"]
+    mg.load_tuning(str(good))
     assert mg.select_config("N", "T", 3000, 5000, 2500, 0) == f32[-1]["id"]   # within 2x
     assert mg.select_config("t", "n", 1000, 2000, 300, 1) == x3[-1]["id"]
     bad_cases = ["nonsense\n", "misgemm-tuning 1\n0 N N 1 1 1 no_such_config\n",
                  "misgemm-tuning 1\n1 N N 64 64 64 %s\n" % f32[0]["name"],  # mode mismatch
                  "misgemm-tuning 1\n0 Q N 64 64 64 %s\n" % f32[0]["name"],
                  "misgemm-tuning 1\n0 N N 0 64 64 %s\n" % f32[0]["name"],
-                 "misgemm-tuning 1\nbatch 0 %s\n" % f32[0]["name"]]  # no persistent variant
+                 "misgemm-tuning 1\nbatch 0 %s\n" % f32[0]["name"],  # no persistent variant
+                 "misgemm-tuning 1\n0 N N 64 64 64 %s 8 2\n" % nosplit["name"],  # no split-K
+                 "misgemm-tuning 1\n0 N N 64 64 64 %s 8 65\n" % split["name"]]
     for i, text in enumerate(bad_cases):
         p = tmp_path / ("bad%d.txt" % i)
         p.write_text(text)
