@@ -29,6 +29,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 U32 = 2.0 ** -24  # unit roundoff of FP32 (round to nearest)
+U64 = 2.0 ** -53  # unit roundoff of FP64
 
 
 def build(force: bool = True) -> str:
@@ -64,6 +65,14 @@ def _bind(lib):
     lib.oracle_bf16x3_split_array.restype = None
     lib.oracle_bf16x3_sweep.argtypes = [ctypes.c_uint64, ctypes.c_uint64, vp, vp, i32]
     lib.oracle_bf16x3_sweep.restype = None
+    f64 = ctypes.c_double
+    lib.oracle_dgemm_f128.argtypes = [ctypes.c_char, ctypes.c_char, i64, i64, i64,
+                                      f64, vp, i64, vp, i64, f64, vp, i64, vp, vp, i32]
+    lib.oracle_dgemm_f128.restype = i32
+    lib.oracle_dgemm_f128_entries.argtypes = [ctypes.c_char, ctypes.c_char, i64, i64, i64,
+                                              f64, vp, i64, vp, i64, f64, vp, i64,
+                                              i64, vp, vp, vp, vp, i32]
+    lib.oracle_dgemm_f128_entries.restype = i32
     lib.oracle_max_threads.argtypes = []
     lib.oracle_max_threads.restype = i32
     return lib
@@ -77,6 +86,12 @@ def _f32(a):
     if a is None:
         return None
     return np.ascontiguousarray(a, dtype=np.float32).reshape(-1)
+
+
+def _f64(a):
+    if a is None:
+        return None
+    return np.ascontiguousarray(a, dtype=np.float64).reshape(-1)
 
 
 class Oracle:
@@ -129,6 +144,41 @@ class Oracle:
                                                _ptr(cref), _ptr(den), nthreads)
         if rc != 0:
             raise ValueError("oracle_sgemm_f64_entries failed with code %d" % rc)
+        return cref, den
+
+    def dgemm_f128(self, transa: str, transb: str, m: int, n: int, k: int, alpha: float,
+                   A: np.ndarray, lda: int, B: np.ndarray, ldb: int, beta: float,
+                   C0: Optional[np.ndarray], ldc: int, nthreads: int = 0
+                   ) -> Tuple[np.ndarray, np.ndarray]:
+        """Double-precision problem (Section IV-B): (Cref, den) as (m, n) float64
+        arrays, evaluated in binary128 from the FP64 inputs and rounded once."""
+        A, B, C0 = _f64(A), _f64(B), _f64(C0)
+        cref = np.zeros((n, m), dtype=np.float64)
+        den = np.zeros((n, m), dtype=np.float64)
+        rc = self.lib.oracle_dgemm_f128(transa.encode(), transb.encode(), m, n, k, alpha,
+                                        _ptr(A), lda, _ptr(B), ldb, beta, _ptr(C0), ldc,
+                                        _ptr(cref), _ptr(den), nthreads)
+        if rc != 0:
+            raise ValueError("oracle_dgemm_f128 failed with code %d" % rc)
+        return cref.T, den.T
+
+    def dgemm_f128_entries(self, transa: str, transb: str, m: int, n: int, k: int,
+                           alpha: float, A: np.ndarray, lda: int, B: np.ndarray, ldb: int,
+                           beta: float, C0: Optional[np.ndarray], ldc: int,
+                           rows: Sequence[int], cols: Sequence[int], nthreads: int = 0
+                           ) -> Tuple[np.ndarray, np.ndarray]:
+        """The dgemm oracle at the entries (rows[e], cols[e])."""
+        A, B, C0 = _f64(A), _f64(B), _f64(C0)
+        r = np.ascontiguousarray(rows, dtype=np.int64)
+        c = np.ascontiguousarray(cols, dtype=np.int64)
+        cref = np.zeros(r.size, dtype=np.float64)
+        den = np.zeros(r.size, dtype=np.float64)
+        rc = self.lib.oracle_dgemm_f128_entries(transa.encode(), transb.encode(), m, n, k,
+                                                alpha, _ptr(A), lda, _ptr(B), ldb, beta,
+                                                _ptr(C0), ldc, r.size, _ptr(r), _ptr(c),
+                                                _ptr(cref), _ptr(den), nthreads)
+        if rc != 0:
+            raise ValueError("oracle_dgemm_f128_entries failed with code %d" % rc)
         return cref, den
 
     def sgemm_bf16x3_f64(self, transa: str, transb: str, m: int, n: int, k: int,
@@ -211,6 +261,14 @@ def sgemm_bf16x3_f64(*args, **kw):
     return _default().sgemm_bf16x3_f64(*args, **kw)
 
 
+def dgemm_f128(*args, **kw):
+    return _default().dgemm_f128(*args, **kw)
+
+
+def dgemm_f128_entries(*args, **kw):
+    return _default().dgemm_f128_entries(*args, **kw)
+
+
 def bf16_rne(x: float) -> int:
     return _default().bf16_rne(x)
 
@@ -243,6 +301,20 @@ def tol(k: int) -> float:
     return max(2 * k, k + 3) * U32
 
 
+def tol_d(k: int) -> float:
+    """The same bound for an FP64 computation: max(2K, K + 3) * 2^-53."""
+    return max(2 * k, k + 3) * U64
+
+
+def tol_false_d(k: int) -> float:
+    """Bound for the FP64 interface computed in FP32 (the paper's "false
+    dgemm"): rounding a and b to FP32 perturbs each product by at most
+    (2u + u^2)|a||b|, then the FP32 sum is held to tol(k) of the rounded
+    operands; tol(k) + 2^-22 covers both with room for the second-order terms.
+    """
+    return tol(k) + 2.0 ** -22
+
+
 def normalized_error(C: np.ndarray, cref: np.ndarray, den: np.ndarray):
     """Elementwise |C - Cref| / den, with den == 0 mapped to 0 where C == Cref
     exactly and to +inf where it does not (a zero denominator demands an exact
@@ -257,10 +329,12 @@ def normalized_error(C: np.ndarray, cref: np.ndarray, den: np.ndarray):
     return out
 
 
-def check(C: np.ndarray, cref: np.ndarray, den: np.ndarray, k: int):
-    """Return (ok, max_err, mean_err, max_err / tol(k))."""
+def check(C: np.ndarray, cref: np.ndarray, den: np.ndarray, k: int, tol_fn=None):
+    """Return (ok, max_err, mean_err, max_err / bound), bound = tol_fn(k)
+    (tol by default)."""
+    bound = (tol_fn or tol)(k)
     e = normalized_error(C, cref, den)
     if e.size == 0:
         return True, 0.0, 0.0, 0.0
     mx = float(np.max(e))
-    return mx <= tol(k), mx, float(np.mean(e)), mx / tol(k)
+    return mx <= bound, mx, float(np.mean(e)), mx / bound

@@ -27,6 +27,12 @@
  * of what the previous parts left over, and the six part products whose part
  * indices sum to at most 2 are kept.
  *
+ * The dgemm functions state the same problem for FP64 storage (the paper's
+ * double-precision variant, Section IV-B): products of two FP64 values are
+ * exact in binary128 (53+53 <= 113 significand bits), the K-sum runs in
+ * binary128 in ascending p, alpha and beta are applied after the sum, and
+ * the result is rounded once to FP64.
+ *
  * Build: gcc -O2 -fopenmp -ffp-contract=off -fPIC -shared (no -ffast-math).
  */
 #include <math.h>
@@ -341,5 +347,88 @@ int oracle_sgemm_bf16x3_f64(char transa, char transb, int64_t m, int64_t n, int6
             Cref[i + j * m] = c;
         }
     free(pa); free(pb);
+    return ORACLE_OK;
+}
+
+/* ------------------------------------------------------------------------
+ * Double-precision GEMM (Section IV-B), evaluated in binary128.
+ * ------------------------------------------------------------------------ */
+typedef __float128 quad;
+
+static quad quad_abs(quad x) { return x < 0 ? -x : x; }
+
+/* Element (i,p) of op(X) for FP64 storage (same indexing as op_elem). */
+static double op_elem_d(const double *X, int64_t ld, int trans, int64_t i, int64_t p)
+{
+    return trans ? X[p + i * ld] : X[i + p * ld];
+}
+
+/* One entry: Cref(i,j) and den(i,j), both rounded once to FP64. */
+static void dgemm_entry(int ta, int tb, int64_t k, double alpha, const double *A, int64_t lda,
+                        const double *B, int64_t ldb, double beta, const double *C0,
+                        int64_t ldc, int use_ab, int64_t i, int64_t j, double *cref,
+                        double *den)
+{
+    quad s = 0, sabs = 0;
+    if (use_ab)
+        for (int64_t p = 0; p < k; ++p) {
+            const quad x = (quad)op_elem_d(A, lda, ta, i, p);
+            const quad y = (quad)op_elem_d(B, ldb, tb, p, j);
+            s += x * y;
+            sabs += quad_abs(x) * quad_abs(y);
+        }
+    quad c = (quad)alpha * s;
+    quad d = quad_abs((quad)alpha) * sabs;
+    if (beta != 0.0) {
+        const quad c0 = (quad)C0[i + j * ldc];
+        c += (quad)beta * c0;
+        d += quad_abs((quad)beta) * quad_abs(c0);
+    }
+    *cref = (double)c;
+    *den = (double)d;
+}
+
+/*
+ * Full dgemm oracle.  Cref and den are m*n FP64 arrays, column-major with
+ * leading dimension m.  C0 may be NULL when beta == 0.  Degenerate cases as
+ * for oracle_sgemm_f64.
+ */
+int oracle_dgemm_f128(char transa, char transb, int64_t m, int64_t n, int64_t k,
+                      double alpha, const double *A, int64_t lda,
+                      const double *B, int64_t ldb,
+                      double beta, const double *C0, int64_t ldc,
+                      double *Cref, double *den, int nthreads)
+{
+    int ta = trans_flag(transa), tb = trans_flag(transb);
+    if (ta < 0 || tb < 0 || m < 0 || n < 0 || k < 0) return ORACLE_BAD_ARG;
+    if (m == 0 || n == 0) return ORACLE_OK;
+    set_threads(nthreads);
+    const int use_ab = (alpha != 0.0 && k > 0);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t i = 0; i < m; ++i)
+            dgemm_entry(ta, tb, k, alpha, A, lda, B, ldb, beta, C0, ldc, use_ab, i, j,
+                        &Cref[i + j * m], &den[i + j * m]);
+    return ORACLE_OK;
+}
+
+/* The dgemm oracle at single entries (rows[e], cols[e]). */
+int oracle_dgemm_f128_entries(char transa, char transb, int64_t m, int64_t n, int64_t k,
+                              double alpha, const double *A, int64_t lda,
+                              const double *B, int64_t ldb,
+                              double beta, const double *C0, int64_t ldc,
+                              int64_t count, const int64_t *rows, const int64_t *cols,
+                              double *cref, double *den, int nthreads)
+{
+    int ta = trans_flag(transa), tb = trans_flag(transb);
+    if (ta < 0 || tb < 0 || m < 0 || n < 0 || k < 0 || count < 0) return ORACLE_BAD_ARG;
+    for (int64_t e = 0; e < count; ++e)
+        if (rows[e] < 0 || rows[e] >= m || cols[e] < 0 || cols[e] >= n) return ORACLE_BAD_ARG;
+    set_threads(nthreads);
+    const int use_ab = (alpha != 0.0 && k > 0);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t e = 0; e < count; ++e)
+        dgemm_entry(ta, tb, k, alpha, A, lda, B, ldb, beta, C0, ldc, use_ab, rows[e], cols[e],
+                    &cref[e], &den[e]);
     return ORACLE_OK;
 }

@@ -27,6 +27,8 @@ import numpy as np
 SEED_BASE = 160805265
 NAN_BITS = np.uint32(0x7FC00000)
 CANARY_BITS = np.uint32(0x7FC0DEAD)
+NAN_BITS64 = np.uint64(0x7FF8000000000000)
+CANARY_BITS64 = np.uint64(0x7FF8DEADDEADDEAD)
 
 
 def seed_for(config: int, case: int) -> int:
@@ -72,7 +74,7 @@ class Problem:
         """Algorithmic HBM bytes: read op(A), op(B) once, read C0 when
         beta != 0, write C once."""
         c_terms = 2 if self.beta != 0.0 else 1
-        return 4 * (self.m * self.k + self.k * self.n + c_terms * self.m * self.n)
+        return self.A.itemsize * (self.m * self.k + self.k * self.n + c_terms * self.m * self.n)
 
 
 def storage_size(rows: int, cols: int, ld: int) -> int:
@@ -116,6 +118,37 @@ def make_problem(transa: str, transb: str, m: int, n: int, k: int, alpha: float,
     if beta == 0.0 and c0_nan_when_beta0:
         C0.view(np.uint32)[:] = NAN_BITS
     fill_padding(C0, m, n, ldc, CANARY_BITS)
+    return Problem(transa, transb, m, n, k, float(alpha), A, lda, B, ldb, float(beta), C0, ldc,
+                   label=label)
+
+
+def fill_padding64(buf: np.ndarray, rows: int, cols: int, ld: int, bits: np.uint64) -> None:
+    """fill_padding for FP64 storage."""
+    if ld > rows and cols > 0:
+        view = buf.view(np.uint64).reshape(cols, ld)
+        view[:, rows:] = bits
+
+
+def make_problem_d(transa: str, transb: str, m: int, n: int, k: int, alpha: float,
+                   beta: float, seed: int, dist: str = "uniform", pad: int = 0,
+                   label: str = "") -> Problem:
+    """One double-precision problem: the draws of make_problem kept in FP64
+    (A, then B, then C0, over the stored arrays), FP64 NaN in the A/B
+    padding and in C0 when beta == 0, an FP64 canary in the C padding."""
+    rng = np.random.default_rng(seed)
+    ar, ac = (k, m) if is_trans(transa) else (m, k)
+    br, bc = (n, k) if is_trans(transb) else (k, n)
+    lda, ldb, ldc = max(1, ar + pad), max(1, br + pad), max(1, m + pad)
+    draw = {"uniform": lambda size: rng.uniform(-1.0, 1.0, size),
+            "normal": lambda size: rng.standard_normal(size)}[dist]
+    A = draw(storage_size(ar, ac, lda)).astype(np.float64)
+    B = draw(storage_size(br, bc, ldb)).astype(np.float64)
+    C0 = draw(storage_size(m, n, ldc)).astype(np.float64)
+    fill_padding64(A, ar, ac, lda, NAN_BITS64)
+    fill_padding64(B, br, bc, ldb, NAN_BITS64)
+    if beta == 0.0:
+        C0.view(np.uint64)[:] = NAN_BITS64
+    fill_padding64(C0, m, n, ldc, CANARY_BITS64)
     return Problem(transa, transb, m, n, k, float(alpha), A, lda, B, ldb, float(beta), C0, ldc,
                    label=label)
 

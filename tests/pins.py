@@ -313,3 +313,148 @@ def pin_bf16x3_method(o):
         assert np.all(np.abs(x - y) <= drop)
         # and the dropped terms are not all zero on such data
         assert np.any(x != y)
+
+
+# ---------------------------------------------------------------------------
+# Double-precision oracle (Section IV-B): the same facts for FP64 inputs, and
+# a cancellation case that an FP64 (not binary128) accumulation gets wrong.
+# ---------------------------------------------------------------------------
+
+def dense_d(buf, rows, cols, ld):
+    if rows == 0 or cols == 0:
+        return np.zeros((rows, cols))
+    return np.asarray(buf, dtype=np.float64).reshape(cols, ld).T[:rows, :]
+
+
+def problem_dense_d(p: wl.Problem):
+    ar, ac = p.a_shape
+    br, bc = p.b_shape
+    a = dense_d(p.A, ar, ac, p.lda)
+    b = dense_d(p.B, br, bc, p.ldb)
+    a = a.T if wl.is_trans(p.transa) else a
+    b = b.T if wl.is_trans(p.transb) else b
+    return a, b, dense_d(p.C0, p.m, p.n, p.ldc)
+
+
+def run_d(o, p: wl.Problem):
+    return o.dgemm_f128(p.transa, p.transb, p.m, p.n, p.k, p.alpha, p.A, p.lda, p.B, p.ldb,
+                        p.beta, p.C0, p.ldc)
+
+
+def pin_dgemm_fraction_bruteforce(o, seed=2):
+    """Exact rational arithmetic on tiny FP64 problems with full 53-bit
+    significands: Cref and den are the exact values rounded once (within
+    half an ulp, plus nothing measurable from the binary128 sum)."""
+    rng = np.random.default_rng(seed)
+    for case in range(24):
+        ta, tb = wl.TRANS_PAIRS[case % 4]
+        m, n, k = (int(v) for v in rng.integers(1, 7, size=3))
+        alpha = [1.0, -1.5, 0.1, 3.0][case % 4]
+        beta = [0.0, 1.0, -0.3, 0.25][(case // 4) % 4]
+        p = wl.make_problem_d(ta, tb, m, n, k, alpha, beta, seed * 1000 + case, pad=case % 3)
+        cref, den = run_d(o, p)
+        a, b, c0 = problem_dense_d(p)
+        for i in range(m):
+            for j in range(n):
+                s = sum((Fraction(a[i, q]) * Fraction(b[q, j]) for q in range(k)), Fraction(0))
+                sa = sum((abs(Fraction(a[i, q]) * Fraction(b[q, j])) for q in range(k)),
+                         Fraction(0))
+                ex = Fraction(alpha) * s
+                exd = abs(Fraction(alpha)) * sa
+                if beta != 0.0:
+                    ex += Fraction(beta) * Fraction(c0[i, j])
+                    exd += abs(Fraction(beta)) * abs(Fraction(c0[i, j]))
+                for got, want in ((cref[i, j], ex), (den[i, j], exd)):
+                    ulp = np.spacing(abs(float(want)))
+                    assert abs(Fraction(got) - want) <= Fraction(0.5001 * ulp), (case, i, j)
+
+
+def pin_dgemm_cancellation(o):
+    """Sums whose FP64 accumulation loses everything: 1 + 2^-60 - 1 is
+    2^-60, and 2^60 + 1 - 2^60 + x is 1 + x."""
+    A = np.array([1.0, 2.0 ** -60, -1.0, 2.0 ** 60, 1.0, -2.0 ** 60, 0.375])
+    B = np.ones(7)
+    cref, _ = o.dgemm_f128("N", "N", 1, 1, 3, 1.0, A[:3], 1, B[:3], 3, 0.0, None, 1)
+    assert cref[0, 0] == 2.0 ** -60
+    cref, _ = o.dgemm_f128("T", "N", 1, 1, 4, 2.0, A[3:], 4, B[3:], 4, 0.0, None, 1)
+    assert cref[0, 0] == 2.0 * 1.375
+
+
+def pin_dgemm_numpy(o, sizes=((67, 45, 129), (1, 90, 17), (40, 1, 300))):
+    """numpy's FP64 matmul (an independent library) agrees within the FP64
+    bound of its own rounding; NaN padding is never read."""
+    for idx, (m, n, k) in enumerate(sizes):
+        for ta, tb in wl.TRANS_PAIRS:
+            p = wl.make_problem_d(ta, tb, m, n, k, 1.25, -0.5, 500 + idx, pad=2)
+            cref, den = run_d(o, p)
+            a, b, c0 = problem_dense_d(p)
+            ref = 1.25 * (a @ b) - 0.5 * c0
+            assert np.all(np.isfinite(cref))
+            assert np.all(np.abs(cref - ref) <= (k + 3) * U53 * den * 1.0001 + 1e-300), (m, n, k)
+
+
+def pin_dgemm_integer_regime(o):
+    """Integers up to 2^20, K = 64: every partial sum is below 2^53, so the
+    result is exact and equals numpy's int64 matmul."""
+    rng = np.random.default_rng(22)
+    for ta, tb in wl.TRANS_PAIRS:
+        m, n, k = 23, 17, 64
+        a = rng.integers(-2 ** 20, 2 ** 20, size=(m, k))
+        b = rng.integers(-2 ** 20, 2 ** 20, size=(k, n))
+        sa = a.T if wl.is_trans(ta) else a
+        sb = b.T if wl.is_trans(tb) else b
+        A = np.asfortranarray(sa, dtype=np.float64).reshape(-1, order="F")
+        B = np.asfortranarray(sb, dtype=np.float64).reshape(-1, order="F")
+        cref, den = o.dgemm_f128(ta, tb, m, n, k, 1.0, A, sa.shape[0], B, sb.shape[0], 0.0,
+                                 None, m)
+        assert np.array_equal(cref, (a @ b).astype(np.float64))
+        assert np.array_equal(den, (np.abs(a) @ np.abs(b)).astype(np.float64))
+
+
+def pin_dgemm_identity_and_degenerate(o):
+    """A permutation times op(B) is op(B) with rows permuted, bit for bit;
+    alpha = 0 or k = 0 never reads A, B; beta = 0 never reads C0."""
+    rng = np.random.default_rng(23)
+    m, k, n = 9, 9, 7
+    perm = rng.permutation(m)
+    P = np.zeros((m, k))
+    P[np.arange(m), perm] = 1.0
+    b = rng.uniform(-1, 1, size=(k, n))
+    for tb in ("N", "T"):
+        sb = b.T if tb == "T" else b
+        B = np.asfortranarray(sb).reshape(-1, order="F")
+        cref, _ = o.dgemm_f128("N", tb, m, n, k, 1.0, P.reshape(-1, order="F"), m, B,
+                               sb.shape[0], 0.0, None, m)
+        assert np.array_equal(cref, b[perm, :])
+    nan = np.full(64, np.nan)
+    c0 = rng.uniform(-1, 1, 12)
+    cref, den = o.dgemm_f128("N", "N", 3, 4, 5, 0.0, nan, 3, nan, 5, -2.0, c0, 3)
+    assert np.array_equal(cref, -2.0 * c0.reshape(4, 3).T)
+    cref, den = o.dgemm_f128("T", "N", 3, 4, 0, 1.0, nan, 1, nan, 1, 0.5, c0, 3)
+    assert np.array_equal(cref, 0.5 * c0.reshape(4, 3).T)
+    p = wl.make_problem_d("N", "N", 5, 6, 7, 1.0, 0.0, 24)   # C0 is NaN
+    cref, _ = run_d(o, p)
+    assert np.all(np.isfinite(cref))
+
+
+def pin_dgemm_transpose_and_entries(o):
+    """T on an explicitly transposed copy equals N bit for bit ('c' as 't');
+    the single-entry oracle equals the full one bit for bit."""
+    p = wl.make_problem_d("N", "N", 31, 29, 37, -0.75, 0.5, 25, pad=1)
+    cref, den = run_d(o, p)
+    a, b, _ = problem_dense_d(p)
+    at = np.asfortranarray(a.T).reshape(-1, order="F")
+    bt = np.asfortranarray(b.T).reshape(-1, order="F")
+    c2, d2 = o.dgemm_f128("c", "t", p.m, p.n, p.k, p.alpha, at, p.k, bt, p.n, p.beta, p.C0,
+                          p.ldc)
+    assert np.array_equal(cref, c2) and np.array_equal(den, d2)
+    rows = np.array([0, 30, 5, 17])
+    cols = np.array([0, 28, 11, 3])
+    ce, de = o.dgemm_f128_entries(p.transa, p.transb, p.m, p.n, p.k, p.alpha, p.A, p.lda,
+                                  p.B, p.ldb, p.beta, p.C0, p.ldc, rows, cols)
+    assert np.array_equal(ce, cref[rows, cols]) and np.array_equal(de, den[rows, cols])
+
+
+ALL_DGEMM_PINS = [pin_dgemm_fraction_bruteforce, pin_dgemm_cancellation, pin_dgemm_numpy,
+                  pin_dgemm_integer_regime, pin_dgemm_identity_and_degenerate,
+                  pin_dgemm_transpose_and_entries]

@@ -37,6 +37,11 @@ MUTANTS = [
     ("split-keeps-two-parts", "    for (int t = 0; t < 3; ++t) {\n        uint16_t h = oracle_bf16_rne(r);",
      "    parts[2] = 0;\n    for (int t = 0; t < 2; ++t) {\n        uint16_t h = oracle_bf16_rne(r);"),
     ("method-keeps-five-products", "for (int v = 0; u + v <= 2; ++v)", "for (int v = 0; u + v <= 2 && u * v < 1; ++v)"),
+    ("dgemm-sum-in-fp64", "    quad s = 0, sabs = 0;", "    double s = 0, sabs = 0;"),
+    ("dgemm-swapped-transpose-index", "    return trans ? X[p + i * ld] : X[i + p * ld];",
+     "    return trans ? X[i + p * ld] : X[p + i * ld];"),
+    ("dgemm-dropped-beta-term", "        c += (quad)beta * c0;\n", ""),
+    ("dgemm-alpha-on-den-only", "    quad c = (quad)alpha * s;", "    quad c = s;"),
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))

@@ -17,6 +17,18 @@ def test_sgemm_pin(o, pin):
     pin(o)
 
 
+@pytest.mark.parametrize("pin", pins.ALL_DGEMM_PINS, ids=lambda f: f.__name__)
+def test_dgemm_pin(o, pin):
+    pin(o)
+
+
+def test_dgemm_bounds():
+    assert oracle.tol_d(4096) == 2 * 4096 * 2.0 ** -53
+    assert oracle.tol_d(2) == 5 * 2.0 ** -53
+    # FP32 computation of FP64 data: the FP32 bound plus the input rounding
+    assert oracle.tol_false_d(100) == oracle.tol(100) + 2.0 ** -22
+
+
 def test_bf16_rne_matches_torch(o):
     pins.pin_bf16_rne_vs_torch(o)
 
