@@ -510,8 +510,11 @@ def batch_line(args, torch, mg):
 
 COPY_BYTES = 1 << 30
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sgemm_dominant8192_hbm_counters.txt")
+# what decides the sgemm kernels and which of them runs: their sources and
+# the packaged tuning table
 KERNEL_SOURCES = ["gemm_tile.hpp", "packed_x3.hpp", "registry.hpp", "aux_kernels.hip",
                   "sgemm_f32.hip", "sgemm_x3.hip", "sgemm_x3k.hip"]
+TUNING_TABLE = os.path.join(ROOT, "paper_1608_05265_amd", "tuning_mi355x.txt")
 
 
 def kernel_sources_hash() -> str:
@@ -520,6 +523,8 @@ def kernel_sources_hash() -> str:
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_1608_05265_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
+    with open(TUNING_TABLE, "rb") as fh:
+        h.update(fh.read())
     return h.hexdigest()[:16]
 
 

@@ -207,6 +207,31 @@ int misgemm_select_config(char transa, char transb, int64_t m, int64_t n, int64_
 int misgemm_load_tuning(const char *path);
 
 /* ---------------------------------------------------------------------------
+ * Double precision (the paper's dgemm variants, Section IV-B).
+ * ------------------------------------------------------------------------- */
+typedef enum {
+    MISGEMM_D_FP64 = 0, /* FP64 matrix cores (v_mfma_f64_16x16x4_f64), FP64 sums */
+    MISGEMM_D_FP32 = 1  /* the paper's "false dgemm": op(A), op(B) rounded to FP32,
+                           product on the FP32 path, alpha/beta in FP64         */
+} misgemm_dmode;
+
+/*
+ * C = alpha * op(A) * op(B) + beta * C for FP64 column-major matrices in
+ * device memory; arguments, transposes, degenerate cases and error codes as
+ * in misgemm_sgemm (-14: dmode not a misgemm_dmode).  MISGEMM_D_FP32 narrows
+ * the stored operands into the library scratch of (device, stream)
+ * ((lda*cols(A) + ldb*cols(B) + m*n) * 4 bytes; MISGEMM_E_CAPTURING when it
+ * would have to grow during capture), so its result carries FP32 rounding:
+ * within tol(K) + 2^-22 of the normalized error bound instead of the FP64
+ * max(2K, K+3) * 2^-53.  MISGEMM_D_FP64 allocates nothing.
+ */
+int misgemm_dgemm(char transa, char transb, int64_t m, int64_t n, int64_t k,
+                  double alpha, const double *A, int64_t lda,
+                  const double *B, int64_t ldb,
+                  double beta, double *C, int64_t ldc,
+                  int dmode, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Batched form: many independent sgemm problems in one persistent launch.
  * ------------------------------------------------------------------------- */
 

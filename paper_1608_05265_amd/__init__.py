@@ -81,6 +81,10 @@ def _load():
     lib.misgemm_sgemm.restype = i32
     lib.misgemm_sgemm_config.argtypes = sig + [i32, i32, vp]
     lib.misgemm_sgemm_config.restype = i32
+    f64 = ctypes.c_double
+    lib.misgemm_dgemm.argtypes = [c, c, i64, i64, i64, f64, vp, i64, vp, i64, f64, vp, i64,
+                                  i32, vp]
+    lib.misgemm_dgemm.restype = i32
     lib.misgemm_sgemm_split.argtypes = sig + [i32, i32, i32, vp]
     lib.misgemm_sgemm_split.restype = i32
     lib.misgemm_sgemm_ws.argtypes = sig + [vp, i64, vp]
@@ -169,6 +173,20 @@ def sgemm_config(transa: str, transb: str, m: int, n: int, k: int, alpha: float,
                                       lda, _ptr(B), ldb, beta, _ptr(C), ldc, _mode(mode),
                                       config_id, group_m, _stream(stream))
     _check(rc, "misgemm_sgemm_config")
+
+
+D_FP64 = 0
+D_FP32 = 1
+
+
+def dgemm(transa: str, transb: str, m: int, n: int, k: int, alpha: float, A, lda: int, B,
+          ldb: int, beta: float, C, ldc: int, dmode=D_FP64, stream=None) -> None:
+    """Double-precision GEMM on float64 tensors: dmode D_FP64 (FP64 matrix
+    cores) or D_FP32 (the FP32-compute "false dgemm")."""
+    rc = _load().misgemm_dgemm(transa.encode(), transb.encode(), m, n, k, float(alpha), _ptr(A),
+                               lda, _ptr(B), ldb, float(beta), _ptr(C), ldc, int(dmode),
+                               _stream(stream))
+    _check(rc, "misgemm_dgemm")
 
 
 def sgemm_split(transa: str, transb: str, m: int, n: int, k: int, alpha: float, A, lda: int,

@@ -23,7 +23,8 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I" + os.path.join(os.path.dirname(HERE), "include")]
 
-SOURCES = ["api.cpp", "aux_kernels.hip", "sgemm_f32.hip", "sgemm_x3.hip", "sgemm_x3k.hip"]
+SOURCES = ["api.cpp", "aux_kernels.hip", "sgemm_f32.hip", "sgemm_x3.hip", "sgemm_x3k.hip",
+           "dgemm.hip"]
 # measurement helper (matrix-core rate probe), a library of its own
 PROBE_SOURCE = "probe_mfma.hip"
 PROBE_LIB = os.path.join(HERE, "libmisgemm_probe.so")

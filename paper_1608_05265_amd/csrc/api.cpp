@@ -12,6 +12,7 @@
 #include <string>
 #include <vector>
 
+#include "dgemm.hpp"
 #include "registry.hpp"
 
 using namespace misgemm;
@@ -417,6 +418,56 @@ int misgemm_sgemm_split(char transa, char transb, int64_t m, int64_t n, int64_t 
     }
     return run_sgemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, mode,
                      config_id, group_m, stream, WS_LIBRARY, nullptr, 0, splits);
+}
+
+int misgemm_dgemm(char transa, char transb, int64_t m, int64_t n, int64_t k, double alpha,
+                  const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
+                  double *C, int64_t ldc, int dmode, void *stream)
+{
+    const int ta = trans_flag(transa), tb = trans_flag(transb);
+    if (ta < 0) return -1;
+    if (tb < 0) return -2;
+    if (m < 0) return -3;
+    if (n < 0) return -4;
+    if (k < 0) return -5;
+    const int64_t arows = ta ? k : m, acols = ta ? m : k;
+    const int64_t brows = tb ? n : k, bcols = tb ? k : n;
+    if (lda < std::max<int64_t>(1, arows)) return -8;
+    if (ldb < std::max<int64_t>(1, brows)) return -10;
+    if (ldc < std::max<int64_t>(1, m)) return -13;
+    if (dmode != MISGEMM_D_FP64 && dmode != MISGEMM_D_FP32) return -14;
+    const bool work = m > 0 && n > 0;
+    const bool reads_ab = work && k > 0 && alpha != 0.0;
+    if (reads_ab && A == nullptr) return -7;
+    if (reads_ab && B == nullptr) return -9;
+    if (work && C == nullptr) return -12;
+    if (m > (int64_t)1 << 40 || n > (int64_t)1 << 40 || k > (int64_t)1 << 40)
+        return MISGEMM_E_TOO_LARGE;
+    if (!work) return 0;
+    if ((alpha == 0.0 || k == 0) && beta == 1.0) return 0;
+    DeviceInfo *dev = nullptr;
+    int rc = current_device(&dev);
+    if (rc != 0) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if (alpha == 0.0 || k == 0) return (int)launch_dscale(beta, C, m, n, ldc, s);
+    if (dmode == MISGEMM_D_FP64)
+        return (int)launch_dgemm_fp64(ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
+                                      dev->cus, s);
+    // FP32 compute: narrow the stored operands (every element up to the last
+    // used one, padding included), sgemm into an m x n FP32 product, widen
+    // with alpha and beta applied in FP64.
+    const int64_t na = lda * (acols - 1) + arows, nb = ldb * (bcols - 1) + brows;
+    const int64_t a_bytes = (na * 4 + 255) / 256 * 256, b_bytes = (nb * 4 + 255) / 256 * 256;
+    char *ws = (char *)library_workspace(a_bytes + b_bytes + m * n * 4, s);
+    if (ws == nullptr) return MISGEMM_E_CAPTURING;
+    float *a32 = (float *)ws, *b32 = (float *)(ws + a_bytes), *p32 = (float *)(ws + a_bytes + b_bytes);
+    hipError_t e = launch_narrow(A, na, a32, s);
+    if (e == hipSuccess) e = launch_narrow(B, nb, b32, s);
+    if (e != hipSuccess) return (int)e;
+    rc = run_sgemm(transa, transb, m, n, k, 1.0f, a32, lda, b32, ldb, 0.0f, p32, m,
+                   MISGEMM_FP32, -1, 0, stream, WS_NONE, nullptr, 0, 1);
+    if (rc != 0) return rc;
+    return (int)launch_widen(p32, m, n, alpha, beta, C, ldc, s);
 }
 
 int64_t misgemm_workspace_size(char transa, char transb, int64_t m, int64_t n, int64_t k,

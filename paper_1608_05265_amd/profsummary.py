@@ -2,10 +2,17 @@
 
     python -m paper_1608_05265_amd.profsummary trace <dir-with-kernel_trace.csv>
     python -m paper_1608_05265_amd.profsummary pmc <dir-with-counter_collection.csv>
+    python -m paper_1608_05265_amd.profsummary dispatch <dir-with-counter_collection.csv>
 
 `trace` groups dispatches by kernel and grid size and prints calls, average,
 minimum and maximum duration in microseconds; `pmc` prints the per-dispatch
-average of every collected counter, also grouped by kernel and grid size.
+average of every collected counter, also grouped by kernel and grid size,
+plus, when SQ_VALU_MFMA_BUSY_CYCLES and GRBM_GUI_ACTIVE were collected, the
+matrix-core busy fraction busy / (SIMDs * GRBM_GUI_ACTIVE / XCDs) (the busy
+counter sums the cycles of every SIMD, GRBM_GUI_ACTIVE sums the active
+cycles of the 8 XCDs; 1024 SIMDs on MI355X); `dispatch` prints every
+dispatch with its counters (for calibration runs that mix kernels of one
+name).
 Kernel names are shortened to the template arguments that identify a tile
 configuration.
 """
@@ -79,12 +86,60 @@ def pmc(d: str):
     return "\n".join(out)
 
 
+SIMDS, XCDS = 1024, 8
+
+
+def mfma_busy(d: str):
+    """Per (kernel, grid): mean matrix-core busy fraction over dispatches."""
+    rows = list(csv.DictReader(open(_find(d, "counter_collection.csv"))))
+    per = collections.OrderedDict()
+    for r in rows:
+        per.setdefault(r["Dispatch_Id"], [short_name(r["Kernel_Name"]), r.get("Grid_Size", "?"),
+                                          collections.defaultdict(float)])
+        per[r["Dispatch_Id"]][2][r["Counter_Name"]] += float(r["Counter_Value"])
+    groups = collections.OrderedDict()
+    for name, grid, c in per.values():
+        if c.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) > 0 and c.get("GRBM_GUI_ACTIVE", 0.0) > 0:
+            frac = c["SQ_VALU_MFMA_BUSY_CYCLES"] / (SIMDS * c["GRBM_GUI_ACTIVE"] / XCDS)
+            groups.setdefault((name, grid), []).append(frac)
+    out = []
+    for (k, g), v in groups.items():
+        out.append("%-58s %-10s %-14s %6d %16.3f" % (k, g, "mfma_busy_frac", len(v),
+                                                     sum(v) / len(v)))
+    return "\n".join(out)
+
+
+def dispatch(d: str):
+    rows = list(csv.DictReader(open(_find(d, "counter_collection.csv"))))
+    per = collections.OrderedDict()
+    for r in rows:
+        key = int(r["Dispatch_Id"])
+        per.setdefault(key, [short_name(r["Kernel_Name"]), r.get("Grid_Size", "?"),
+                             collections.OrderedDict()])
+        c = per[key][2]
+        c[r["Counter_Name"]] = c.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    out = ["%-6s %-58s %-10s %s" % ("disp", "kernel", "grid", "counters")]
+    for key in sorted(per):
+        name, grid, c = per[key]
+        out.append("%-6d %-58s %-10s %s" % (key, name, grid,
+                                            " ".join("%s=%.1f" % kv for kv in c.items())))
+    return "\n".join(out)
+
+
 def main(argv=None):
     argv = sys.argv[1:] if argv is None else argv
-    if len(argv) != 2 or argv[0] not in ("trace", "pmc"):
+    if len(argv) != 2 or argv[0] not in ("trace", "pmc", "dispatch"):
         print(__doc__)
         return 2
-    print(trace(argv[1]) if argv[0] == "trace" else pmc(argv[1]))
+    if argv[0] == "trace":
+        print(trace(argv[1]))
+    elif argv[0] == "pmc":
+        print(pmc(argv[1]))
+        extra = mfma_busy(argv[1])
+        if extra:
+            print(extra)
+    else:
+        print(dispatch(argv[1]))
     return 0
 
 
