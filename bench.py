@@ -34,6 +34,7 @@ METRIC = "SGEMM TFLOP/s and % of MFMA peak, native FP32 vs bf16x3 at stated erro
 PEAK_FP32 = 157.3      # TFLOP/s, MI355X dense FP32 matrix (= FP32 vector)
 PEAK_BF16 = 2516.6     # TFLOP/s, MI355X dense BF16 matrix
 PEAK_HBM = 8000.0      # GB/s
+PEAK_FP64 = 78.6       # TFLOP/s, MI355X dense FP64 matrix
 
 
 def parse():
@@ -42,7 +43,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="square",
-                    choices=["square", "c1", "rankk", "wide", "batch", "dominant", "peak"],
+                    choices=["square", "c1", "rankk", "wide", "batch", "dominant", "peak",
+                             "dgemm"],
                     help="dominant: only the 8192^3 NN problem of the square sweep in both "
                          "forms plus a 1 GiB device copy, for counter collection")
     ap.add_argument("--no-cpu-baseline", action="store_true",
@@ -508,6 +510,114 @@ def batch_line(args, torch, mg):
     return line
 
 
+def dgemm_line(args, torch, mg):
+    """Double precision (the paper's dgemm, Section IV-B): M = N = K in
+    {2048, 4096, 8192}, NN, alpha = 1.5, beta = -0.5, ld + 16, in both forms
+    (FP64 matrix cores: the line's value; FP32 compute, the paper's "false
+    dgemm": the fp32_compute object); errors and the CPU baseline from the
+    binary128 oracle on sampled entries."""
+    from paper_1608_05265_amd import workloads as wl
+    dev = torch.device("cuda:0")
+    probs = [wl.config6(sz) for sz in wl.DGEMM_SIZES]
+    tens = [(torch.from_numpy(p.A).to(dev), torch.from_numpy(p.B).to(dev),
+             torch.from_numpy(p.C0).to(dev)) for p in probs]
+    flops_step = sum(2.0 * p.m * p.n * p.k for p in probs)
+    stream = torch.cuda.current_stream()
+
+    def call(i, dmode):
+        p = probs[i]
+        A, B, C = tens[i]
+        mg.dgemm(p.transa, p.transb, p.m, p.n, p.k, p.alpha, A, p.lda, B, p.ldb, p.beta, C,
+                 p.ldc, dmode)
+
+    out = {}
+    for dmode, name in ((mg.D_FP64, "fp64"), (mg.D_FP32, "fp32_compute")):
+        for _ in range(args.warmup):
+            for i in range(len(probs)):
+                call(i, dmode)
+        torch.cuda.synchronize()
+        evs = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            for i in range(len(probs)):
+                if i == len(probs) - 1:
+                    s_ = torch.cuda.Event(enable_timing=True)
+                    e_ = torch.cuda.Event(enable_timing=True)
+                    s_.record(stream)
+                    call(i, dmode)
+                    e_.record(stream)
+                    evs.append((s_, e_))
+                else:
+                    call(i, dmode)
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t0
+        dom = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+        pd = probs[-1]
+        out[name] = {"tflops": flops_step * args.steps / total / 1e12,
+                     "ms_per_step": total / args.steps * 1e3, "dominant_avg_ms": dom,
+                     "dominant_tflops": 2.0 * pd.m * pd.n * pd.k / (dom * 1e-3) / 1e12,
+                     "clock": clock_probe(torch, lambda: call(len(probs) - 1, dmode))}
+    f64 = out["fp64"]
+    pd = probs[-1]
+    line = {
+        "metric": METRIC, "value": round(f64["tflops"], 3), "unit": "TFLOP/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(f64["ms_per_step"], 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "dgemm M=N=K in {2048,4096,8192}, NN, alpha=1.5, beta=-0.5, "
+                               "ld=rows+16, uniform[-1,1], FP64 storage",
+                   "flops_per_step": flops_step},
+        "pct_of_fp64_peak": round(100.0 * f64["tflops"] / PEAK_FP64, 2),
+        "fp32_compute": {"value": round(out["fp32_compute"]["tflops"], 3),
+                         "pct_of_fp32_peak": round(100.0 * out["fp32_compute"]["tflops"] /
+                                                   PEAK_FP32, 2),
+                         "dominant_tflops": round(out["fp32_compute"]["dominant_tflops"], 2)},
+        "roofline": {"bound": "mfma", "kernel": "FP64 MFMA tile kernel, %dx%dx%d NN"
+                                                % (pd.m, pd.n, pd.k),
+                     "achieved": round(f64["dominant_tflops"], 3), "peak": PEAK_FP64,
+                     "unit": "TFLOP/s", "frac": round(f64["dominant_tflops"] / PEAK_FP64, 4),
+                     "avg_launch_ms": round(f64["dominant_avg_ms"], 4),
+                     "flops_per_launch": 2.0 * pd.m * pd.n * pd.k, "traffic": None},
+        "clock": {k: v["clock"] for k, v in out.items()},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        cores = len(os.sched_getaffinity(0))
+        errs = {}
+        t_or = 0.0
+        fl_or = 0.0
+        for i, p in enumerate(probs):
+            rng = np.random.default_rng(31 + i)
+            rows = rng.integers(0, p.m, 1024)
+            cols = rng.integers(0, p.n, 1024)
+            t0 = time.perf_counter()
+            cref, den = oracle.dgemm_f128_entries(p.transa, p.transb, p.m, p.n, p.k, p.alpha,
+                                                  p.A, p.lda, p.B, p.ldb, p.beta, p.C0, p.ldc,
+                                                  rows, cols, nthreads=cores)
+            t_or += time.perf_counter() - t0
+            fl_or += 2.0 * p.k * rows.size
+            for dmode, name, tol_fn in ((mg.D_FP64, "fp64", oracle.tol_d),
+                                        (mg.D_FP32, "fp32_compute", oracle.tol_false_d)):
+                A, B, C = tens[i]
+                C.copy_(torch.from_numpy(p.C0).to(dev))
+                call(i, dmode)
+                torch.cuda.synchronize()
+                got = C.cpu().numpy()[rows + cols * p.ldc]
+                ok, mx, mean, ratio = oracle.check(got, cref, den, p.k, tol_fn)
+                e = errs.setdefault(name, {"max_norm_err": 0.0, "max_over_bound": 0.0,
+                                           "within_bound": True, "entries_per_problem": 1024})
+                e["max_norm_err"] = max(e["max_norm_err"], mx)
+                e["max_over_bound"] = max(e["max_over_bound"], ratio)
+                e["within_bound"] = e["within_bound"] and bool(ok)
+        line["error"] = errs
+        line["cpu_baseline"] = {"value": fl_or / t_or / 1e12, "unit": "TFLOP/s", "cores": cores,
+                                "kind": "oracle",
+                                "sample": "binary128 oracle on 1024 sampled entries of each "
+                                          "problem (one length-K dot product with |A||B| per "
+                                          "entry); rate = 2K per entry / time"}
+    return line
+
+
 COPY_BYTES = 1 << 30
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sgemm_dominant8192_hbm_counters.txt")
 # what decides the sgemm kernels and which of them runs: their sources and
@@ -579,6 +689,9 @@ def main():
         return
     if args.workload == "dominant":
         dominant_only(args, torch, mg)
+        return
+    if args.workload == "dgemm":
+        print(json.dumps(dgemm_line(args, torch, mg)))
         return
     if args.workload == "peak":
         print(json.dumps({"workload": "peak", "spec_tflops": {"fp32": PEAK_FP32,

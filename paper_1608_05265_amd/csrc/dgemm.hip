@@ -20,14 +20,16 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 // ---------------------------------------------------------------------------
 // FP64 staging: LDS holds X as Xs[kk][r] (r contiguous, row length LD
 // doubles).  A chunk is two consecutive elements along the stored
-// contiguous direction (one 16-byte load).  LD = R + 16: the two K rows that
-// one ds_read_b64 of 32 lanes touches start 32 banks apart.
+// contiguous direction (one 16-byte load).  Row length: R + 16 (even, for
+// the 16-byte stores) when r is the stored contiguous direction; R + 17 when
+// the slice is transposed on the way in, so that the 8-byte stores of 16
+// lanes (eight k values times two rows) hit 16 distinct bank pairs.
 // ---------------------------------------------------------------------------
 template <int R, int BK, int NT, bool KC>
 struct StageF64 {
     static constexpr int CH = R * BK / 2;            // 2-element chunks per tile
     static constexpr int S = (CH + NT - 1) / NT;
-    static constexpr int LD = R + 16;
+    static constexpr int LD = KC ? R + 17 : R + 16;
     static constexpr int ELEMS = BK * LD;
     doublex2 v[S];
 
@@ -90,14 +92,16 @@ struct DArgs {
     double *C;
     int64_t lda, ldb, ldc;
     double alpha, beta;
-    int vec_a, vec_b, vec_c;  // 16-byte access legal (aligned base, even ld)
+    int vec_a, vec_b;  // 16-byte loads legal (aligned base, even ld)
 };
 
 // ---------------------------------------------------------------------------
 // FP64 tile: BM x BN per workgroup, waves of WM x WN made of 16x16 MFMA
 // blocks.  Operand layout of v_mfma_f64_16x16x4_f64 for lane l: A element
-// (row l%16, k l/16), B element (k l/16, column l%16); the 16x16 result
-// gives lane l rows 4*(l/16)+e, e = 0..3, of column l%16.
+// (row l%16, k l/16), B element (k l/16, column l%16); result element e of
+// lane l is row l/16 + 4e of column l%16 (measured on the device with
+// one-hot operands: unlike the FP32 16x16 layout, a lane's four rows are
+// spaced by four).
 // ---------------------------------------------------------------------------
 template <class SH, bool TA, bool TB>
 struct F64Tile {
@@ -120,30 +124,15 @@ struct F64Tile {
             double *cc = g.C + col * g.ldc;
 #pragma unroll
             for (int i = 0; i < RM; ++i) {
-                const int64_t row = row0 + i * 16 + q * 4;
-                if (row >= g.m) continue;
-                double out[4];
 #pragma unroll
-                for (int e = 0; e < 4; ++e) out[e] = g.alpha * acc[i][j][e];
-                if (g.vec_c && row + 4 <= g.m) {
-                    doublex2 *p = reinterpret_cast<doublex2 *>(cc + row);
-                    if (use_c0) {
-                        const doublex2 c0 = p[0], c1 = p[1];
-                        out[0] += g.beta * c0[0];
-                        out[1] += g.beta * c0[1];
-                        out[2] += g.beta * c1[0];
-                        out[3] += g.beta * c1[1];
-                    }
-                    p[0] = doublex2{out[0], out[1]};
-                    p[1] = doublex2{out[2], out[3]};
-                } else {
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        if (row + e < g.m) {
-                            double o = out[e];
-                            if (use_c0) o += g.beta * cc[row + e];
-                            cc[row + e] = o;
-                        }
+                for (int e = 0; e < 4; ++e) {
+                    // lanes q = 0..3 of a column hold rows 4e + q: each store
+                    // instruction writes 32 contiguous bytes per column
+                    const int64_t row = row0 + i * 16 + 4 * e + q;
+                    if (row < g.m) {
+                        double o = g.alpha * acc[i][j][e];
+                        if (use_c0) o += g.beta * cc[row];
+                        cc[row] = o;
                     }
                 }
             }
@@ -258,7 +247,6 @@ hipError_t launch_dgemm_fp64(int ta, int tb, int64_t m, int64_t n, int64_t k, do
     g.alpha = alpha; g.beta = beta;
     g.vec_a = ((uintptr_t)A & 15u) == 0 && lda % 2 == 0;
     g.vec_b = ((uintptr_t)B & 15u) == 0 && ldb % 2 == 0;
-    g.vec_c = ((uintptr_t)C & 15u) == 0 && ldc % 2 == 0;
     const int64_t big = ((m + 127) / 128) * ((n + 127) / 128);
     if (big >= cus) return launch_dgemm_shape<DShapeL>(ta, tb, g, s);
     return launch_dgemm_shape<DShapeS>(ta, tb, g, s);

@@ -224,6 +224,19 @@ def config5(count: int = 512, seed_case: int = 0, lo: int = 2, hi: int = 64,
             for i, s in enumerate(specs)]
 
 
+DGEMM_SIZES = [2048, 4096, 8192]
+
+
+def config6(size: int, transa: str = "N", transb: str = "N") -> Problem:
+    """Double-precision square problem (the paper's dgemm, Section IV-B, at
+    the square-sweep settings): alpha=1.5, beta=-0.5, uniform[-1,1], every
+    leading dimension padded by 16."""
+    case = DGEMM_SIZES.index(size) * 4 + TRANS_PAIRS.index((transa, transb)) \
+        if size in DGEMM_SIZES else 1000 + size
+    return make_problem_d(transa, transb, size, size, size, 1.5, -0.5, seed_for(6, case),
+                          pad=16, label="dgemm%d_%s%s" % (size, transa, transb))
+
+
 def gflops_rate(m: int, n: int, k: int, seconds: float) -> float:
     """GFLOP/s = 2*m*n*k / t / 1e9 (the convention behind the paper's tables)."""
     return 2.0 * m * n * k / seconds / 1e9

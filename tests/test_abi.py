@@ -97,6 +97,16 @@ def test_quick_returns_need_no_device(mg):
                                    -1, -1, 2, None) == -16
     assert lib.misgemm_sgemm_split(b"N", b"N", 0, 5, 5, 1.0, None, 1, None, 5, 0.0, None, 1, 0,
                                    -1, 0, 4, None) == 0
+    # dgemm: the same argument positions, checked before any HIP call
+    dargs = [b"N", b"N", 8, 6, 5, 1.0, 0x1000, 8, 0x2000, 5, 0.0, 0x3000, 8]
+    for pos, val, code in [(0, b"X", -1), (1, b"Q", -2), (2, -1, -3), (3, -1, -4),
+                           (4, -1, -5), (7, 3, -8), (9, 3, -10), (12, 3, -13)]:
+        a = list(dargs)
+        a[pos] = val
+        assert lib.misgemm_dgemm(*a, 0, None) == code
+    assert lib.misgemm_dgemm(*dargs, 7, None) == -14
+    assert lib.misgemm_dgemm(b"N", b"N", 0, 5, 5, 1.0, None, 1, None, 5, 0.0, None, 1, 0,
+                             None) == 0
     assert lib.misgemm_bf16x3_split(None, 0, None, None) == 0
     assert lib.misgemm_bf16x3_split(None, 3, None, None) == -1
     assert lib.misgemm_batch_launch(None, None) == 1005
