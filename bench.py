@@ -44,7 +44,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="square",
                     choices=["square", "c1", "rankk", "wide", "batch", "dominant", "peak",
-                             "dgemm"],
+                             "dgemm", "host"],
                     help="dominant: only the 8192^3 NN problem of the square sweep in both "
                          "forms plus a 1 GiB device copy, for counter collection")
     ap.add_argument("--no-cpu-baseline", action="store_true",
@@ -618,6 +618,47 @@ def dgemm_line(args, torch, mg):
     return line
 
 
+def host_line(args, torch, mg):
+    """Host-pointer sgemm (the Fortran-style drop-in): square NN problems at
+    4096^3 and 8192^3 with padded leading dimensions (C then moves column by
+    column) and 8192^3 with tight ones, operands and result in host memory;
+    the rate includes every PCIe transfer (A, B and C0 in, C out) and is
+    compared with the device-resident rate of the same call."""
+    from paper_1608_05265_amd import workloads as wl
+    rows = []
+    for size, pad in ((4096, 16), (8192, 16), (8192, 0)):
+        p = wl.make_problem("N", "N", size, size, size, 1.5, -0.5, wl.seed_for(2, 100 + size),
+                            pad=pad, label="host%d_pad%d" % (size, pad))
+        C = p.C0.copy()
+        call = lambda: mg.sgemm_host("N", "N", p.m, p.n, p.k, p.alpha, p.A, p.lda, p.B, p.ldb,
+                                     p.beta, C, p.ldc)
+        for _ in range(args.warmup):
+            call()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            call()
+        dt = (time.perf_counter() - t0) / args.steps
+        moved = 4.0 * (p.lda * p.k + p.ldb * p.n + 2 * p.m * p.n)
+        r = Resident(p, torch.device("cuda:0"))
+        torch.cuda.synchronize()
+        s_ = torch.cuda.Event(enable_timing=True)
+        e_ = torch.cuda.Event(enable_timing=True)
+        r.call(mg, mg.FP32)
+        s_.record()
+        for _ in range(args.steps):
+            r.call(mg, mg.FP32)
+        e_.record()
+        torch.cuda.synchronize()
+        dev_ms = s_.elapsed_time(e_) / args.steps
+        rows.append({"size": size, "ld_pad": pad, "host_tflops": round(p.flops() / dt / 1e12, 2),
+                     "host_ms": round(dt * 1e3, 3), "pcie_bytes": moved,
+                     "effective_gb_s": round(moved / dt / 1e9, 1),
+                     "device_tflops": round(p.flops() / (dev_ms * 1e-3) / 1e12, 2)})
+        del r
+    return {"workload": "host-pointer sgemm (square sweep problems, NN, FP32), PCIe-inclusive",
+            "rows": rows}
+
+
 COPY_BYTES = 1 << 30
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sgemm_dominant8192_hbm_counters.txt")
 # what decides the sgemm kernels and which of them runs: their sources and
@@ -689,6 +730,9 @@ def main():
         return
     if args.workload == "dominant":
         dominant_only(args, torch, mg)
+        return
+    if args.workload == "host":
+        print(json.dumps(host_line(args, torch, mg)))
         return
     if args.workload == "dgemm":
         print(json.dumps(dgemm_line(args, torch, mg)))

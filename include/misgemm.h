@@ -232,6 +232,46 @@ int misgemm_dgemm(char transa, char transb, int64_t m, int64_t n, int64_t k,
                   int dmode, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Host-pointer BLAS: for callers whose matrices live in host memory, as the
+ * paper's library served unmodified BLAS users (Sections III-A, III-C).
+ * ------------------------------------------------------------------------- */
+
+/*
+ * misgemm_sgemm / misgemm_dgemm on host matrices, synchronous: A and B are
+ * copied into device buffers the library keeps per device (grow-only), C is
+ * cut into column panels (about four when n >= 1024) and panel p+1 is copied
+ * in while panel p is multiplied and panel p-1 copied back, on two streams
+ * of the library's own.  Only the m rows of each column of C are written
+ * (padding rows untouched) and nothing past the last column of any operand
+ * is read.  Calls on one device are serialized.  Returns 0 or an error as
+ * misgemm_sgemm / misgemm_dgemm (-14: mode).
+ */
+int misgemm_sgemm_host(char transa, char transb, int64_t m, int64_t n, int64_t k,
+                       float alpha, const float *A, int64_t lda,
+                       const float *B, int64_t ldb,
+                       float beta, float *C, int64_t ldc, int mode);
+int misgemm_dgemm_host(char transa, char transb, int64_t m, int64_t n, int64_t k,
+                       double alpha, const double *A, int64_t lda,
+                       const double *B, int64_t ldb,
+                       double beta, double *C, int64_t ldc, int dmode);
+
+/*
+ * The classic Fortran BLAS symbols (every argument by reference, 32-bit
+ * integers; trailing hidden string lengths are ignored), on host matrices,
+ * through the two functions above: sgemm_ in MISGEMM_FP32 mode (the
+ * environment variable MISGEMM_SGEMM_MODE=bf16x3 selects the split form),
+ * dgemm_ on FP64 matrix cores.  An invalid argument prints the reference
+ * BLAS message " ** On entry to SGEMM  parameter number N had an illegal
+ * value" to stderr and returns without touching C.
+ */
+void sgemm_(const char *transa, const char *transb, const int *m, const int *n, const int *k,
+            const float *alpha, const float *A, const int *lda, const float *B, const int *ldb,
+            const float *beta, float *C, const int *ldc);
+void dgemm_(const char *transa, const char *transb, const int *m, const int *n, const int *k,
+            const double *alpha, const double *A, const int *lda, const double *B,
+            const int *ldb, const double *beta, double *C, const int *ldc);
+
+/* ---------------------------------------------------------------------------
  * Batched form: many independent sgemm problems in one persistent launch.
  * ------------------------------------------------------------------------- */
 

@@ -85,6 +85,11 @@ def _load():
     lib.misgemm_dgemm.argtypes = [c, c, i64, i64, i64, f64, vp, i64, vp, i64, f64, vp, i64,
                                   i32, vp]
     lib.misgemm_dgemm.restype = i32
+    lib.misgemm_sgemm_host.argtypes = sig
+    lib.misgemm_sgemm_host.restype = i32
+    lib.misgemm_dgemm_host.argtypes = [c, c, i64, i64, i64, f64, vp, i64, vp, i64, f64, vp, i64,
+                                       i32]
+    lib.misgemm_dgemm_host.restype = i32
     lib.misgemm_sgemm_split.argtypes = sig + [i32, i32, i32, vp]
     lib.misgemm_sgemm_split.restype = i32
     lib.misgemm_sgemm_ws.argtypes = sig + [vp, i64, vp]
@@ -187,6 +192,35 @@ def dgemm(transa: str, transb: str, m: int, n: int, k: int, alpha: float, A, lda
                                lda, _ptr(B), ldb, float(beta), _ptr(C), ldc, int(dmode),
                                _stream(stream))
     _check(rc, "misgemm_dgemm")
+
+
+def _host_ptr(a, dtype):
+    import numpy as np
+    if a is None:
+        return None
+    if not (isinstance(a, np.ndarray) and a.dtype == dtype and a.flags["C_CONTIGUOUS"]):
+        raise TypeError("host operands must be contiguous numpy arrays of %s" % np.dtype(dtype))
+    return a.ctypes.data
+
+
+def sgemm_host(transa: str, transb: str, m: int, n: int, k: int, alpha: float, A, lda: int, B,
+               ldb: int, beta: float, C, ldc: int, mode=FP32) -> None:
+    """sgemm on host (numpy float32) column-major storage; C updated in place."""
+    import numpy as np
+    rc = _load().misgemm_sgemm_host(transa.encode(), transb.encode(), m, n, k, alpha,
+                                    _host_ptr(A, np.float32), lda, _host_ptr(B, np.float32), ldb,
+                                    beta, _host_ptr(C, np.float32), ldc, _mode(mode))
+    _check(rc, "misgemm_sgemm_host")
+
+
+def dgemm_host(transa: str, transb: str, m: int, n: int, k: int, alpha: float, A, lda: int, B,
+               ldb: int, beta: float, C, ldc: int, dmode=D_FP64) -> None:
+    """dgemm on host (numpy float64) column-major storage; C updated in place."""
+    import numpy as np
+    rc = _load().misgemm_dgemm_host(transa.encode(), transb.encode(), m, n, k, float(alpha),
+                                    _host_ptr(A, np.float64), lda, _host_ptr(B, np.float64), ldb,
+                                    float(beta), _host_ptr(C, np.float64), ldc, int(dmode))
+    _check(rc, "misgemm_dgemm_host")
 
 
 def sgemm_split(transa: str, transb: str, m: int, n: int, k: int, alpha: float, A, lda: int,

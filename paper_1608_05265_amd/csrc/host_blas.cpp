@@ -1,0 +1,239 @@
+// Host-pointer BLAS entry points: the classic Fortran sgemm_/dgemm_ symbols
+// (every argument by reference) and their C forms with a status code.  The
+// paper's library served unmodified BLAS callers and overlapped the
+// host/co-processor transfers with the multiplications (Sections III-A and
+// III-C); here the operands travel over PCIe into HBM, C is cut into column
+// panels, and panel p+1 is copied in while panel p is multiplied and panel
+// p-1 is copied back.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+
+#include "../../include/misgemm.h"
+
+namespace {
+
+int trans_of(char t)
+{
+    if (t == 'N' || t == 'n') return 0;
+    if (t == 'T' || t == 't' || t == 'C' || t == 'c') return 1;
+    return -1;
+}
+
+// Per-device state: two streams (copies, compute) and grow-only device
+// buffers for A, B and C.  Calls on one device are serialized.
+struct HostState {
+    std::mutex mu;
+    bool init = false;
+    hipStream_t copy = nullptr, comp = nullptr;
+    void *buf[3] = {nullptr, nullptr, nullptr};
+    size_t cap[3] = {0, 0, 0};
+};
+constexpr int MAX_DEV = 64;
+HostState g_host[MAX_DEV];
+
+int ensure(HostState &h, int which, size_t bytes, void **out)
+{
+    if (h.cap[which] < bytes) {
+        if (h.buf[which]) (void)hipFree(h.buf[which]);
+        h.buf[which] = nullptr;
+        h.cap[which] = 0;
+        hipError_t e = hipMalloc(&h.buf[which], bytes);
+        if (e != hipSuccess) return (int)e;
+        h.cap[which] = bytes;
+    }
+    *out = h.buf[which];
+    return 0;
+}
+
+// Copy the rows x cols column-major block with leading dimension ld
+// between host and device, keeping the same leading dimension on the
+// device.  Never past the last column's last row.  An operand that is only
+// read may travel as one contiguous range, padding rows included (one large
+// transfer instead of one per column); C (may_touch_padding false) moves
+// as rows x cols, so that padding rows of the host C -- which may belong to
+// a larger matrix that other code is using -- are never written.
+template <class T>
+hipError_t copy_block(T *dst, const T *src, int64_t rows, int64_t cols, int64_t ld,
+                      hipMemcpyKind kind, hipStream_t s, bool may_touch_padding)
+{
+    if (rows == 0 || cols == 0) return hipSuccess;
+    if (ld == rows || may_touch_padding)
+        return hipMemcpyAsync(dst, src, (size_t)(ld * (cols - 1) + rows) * sizeof(T), kind, s);
+    return hipMemcpy2DAsync(dst, (size_t)ld * sizeof(T), src, (size_t)ld * sizeof(T),
+                            (size_t)rows * sizeof(T), (size_t)cols, kind, s);
+}
+
+// Panels of C columns: about four when n is large, so that copies overlap
+// the multiplications, each at least 256 columns wide.
+int64_t panel_width(int64_t n)
+{
+    if (n < 1024) return std::max<int64_t>(n, 1);
+    return (n + 3) / 4;
+}
+
+template <class T, class GEMM>
+int host_gemm(char transa, char transb, int64_t m, int64_t n, int64_t k, T alpha,
+              const T *A, int64_t lda, const T *B, int64_t ldb, T beta, T *C, int64_t ldc,
+              GEMM gemm)
+{
+    const int ta = trans_of(transa), tb = trans_of(transb);
+    if (ta < 0) return -1;
+    if (tb < 0) return -2;
+    if (m < 0) return -3;
+    if (n < 0) return -4;
+    if (k < 0) return -5;
+    const int64_t arows = ta ? k : m, acols = ta ? m : k;
+    const int64_t brows = tb ? n : k, bcols = tb ? k : n;
+    if (lda < std::max<int64_t>(1, arows)) return -8;
+    if (ldb < std::max<int64_t>(1, brows)) return -10;
+    if (ldc < std::max<int64_t>(1, m)) return -13;
+    const bool reads_ab = m > 0 && n > 0 && k > 0 && alpha != T(0);
+    if (reads_ab && A == nullptr) return -7;
+    if (reads_ab && B == nullptr) return -9;
+    if (m > 0 && n > 0 && C == nullptr) return -12;
+    if (m == 0 || n == 0) return 0;
+    if (!reads_ab && beta == T(1)) return 0;
+
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEV) return MISGEMM_E_NO_DEVICE;
+    HostState &h = g_host[dev];
+    std::lock_guard<std::mutex> lock(h.mu);
+    if (!h.init) {
+        if (hipStreamCreateWithFlags(&h.copy, hipStreamNonBlocking) != hipSuccess ||
+            hipStreamCreateWithFlags(&h.comp, hipStreamNonBlocking) != hipSuccess)
+            return MISGEMM_E_NO_DEVICE;
+        h.init = true;
+    }
+    void *dA = nullptr, *dB = nullptr, *dC = nullptr;
+    int rc = 0;
+    if (reads_ab) {
+        rc = ensure(h, 0, (size_t)(lda * (acols - 1) + arows) * sizeof(T), &dA);
+        if (rc == 0) rc = ensure(h, 1, (size_t)(ldb * (bcols - 1) + brows) * sizeof(T), &dB);
+    }
+    if (rc == 0) rc = ensure(h, 2, (size_t)(ldc * (n - 1) + m) * sizeof(T), &dC);
+    if (rc != 0) return rc;
+    T *a = (T *)dA, *b = (T *)dB, *c = (T *)dC;
+
+    hipError_t e = hipSuccess;
+    // A whole; B whole when its stored columns are not C's columns (transb)
+    if (reads_ab) {
+        e = copy_block(a, A, arows, acols, lda, hipMemcpyHostToDevice, h.copy, true);
+        if (e == hipSuccess && tb)
+            e = copy_block(b, B, brows, bcols, ldb, hipMemcpyHostToDevice, h.copy, true);
+    }
+    const int64_t nb = panel_width(n);
+    const int64_t panels = (n + nb - 1) / nb;
+    constexpr int nev = 4;
+    hipEvent_t in_done[nev] = {}, out_done[nev] = {};
+    for (int i = 0; i < nev && e == hipSuccess; ++i) {
+        e = hipEventCreateWithFlags(&in_done[i], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&out_done[i], hipEventDisableTiming);
+    }
+    for (int64_t p = 0; p < panels && e == hipSuccess && rc == 0; ++p) {
+        const int64_t j0 = p * nb, cols = std::min(nb, n - j0);
+        const int slot = (int)(p % nev);
+        // stage panel p (its own device columns, so no panel waits for
+        // another): B columns (transb = N), C columns when beta != 0
+        if (reads_ab && !tb)
+            e = copy_block(b + j0 * ldb, B + j0 * ldb, brows, cols, ldb, hipMemcpyHostToDevice,
+                           h.copy, true);
+        if (e == hipSuccess && beta != T(0))
+            e = copy_block(c + j0 * ldc, C + j0 * ldc, m, cols, ldc, hipMemcpyHostToDevice,
+                           h.copy, false);
+        if (e == hipSuccess) e = hipEventRecord(in_done[slot], h.copy);
+        if (e == hipSuccess) e = hipStreamWaitEvent(h.comp, in_done[slot], 0);
+        if (e != hipSuccess) break;
+        // multiply panel p on the compute stream
+        const T *bp = tb ? b + j0 : b + j0 * ldb;  // op(B)(:, j0:j0+cols)
+        rc = gemm(transa, transb, m, cols, k, alpha, a, lda, bp, ldb, beta, c + j0 * ldc, ldc,
+                  (void *)h.comp);
+        if (rc != 0) break;
+        e = hipEventRecord(out_done[slot], h.comp);
+        if (e == hipSuccess) e = hipStreamWaitEvent(h.copy, out_done[slot], 0);
+        // copy panel p back (only its m rows: the host padding stays untouched)
+        if (e == hipSuccess)
+            e = copy_block(C + j0 * ldc, c + j0 * ldc, m, cols, ldc, hipMemcpyDeviceToHost,
+                           h.copy, false);
+        if (e == hipSuccess) e = hipEventRecord(out_done[slot], h.copy);
+    }
+    const hipError_t s1 = hipStreamSynchronize(h.comp), s2 = hipStreamSynchronize(h.copy);
+    for (int i = 0; i < nev; ++i) {
+        if (in_done[i]) (void)hipEventDestroy(in_done[i]);
+        if (out_done[i]) (void)hipEventDestroy(out_done[i]);
+    }
+    if (rc != 0) return rc;
+    if (e != hipSuccess) return (int)e;
+    if (s1 != hipSuccess) return (int)s1;
+    return (int)s2;
+}
+
+void report(const char *name, int rc)
+{
+    if (rc < 0)
+        fprintf(stderr, " ** On entry to %s parameter number %d had an illegal value\n", name,
+                -rc);
+    else if (rc > 0)
+        fprintf(stderr, " ** %s failed: %s\n", name, misgemm_status_string(rc));
+}
+
+int host_mode()
+{
+    const char *e = getenv("MISGEMM_SGEMM_MODE");
+    return e && strcmp(e, "bf16x3") == 0 ? MISGEMM_BF16X3 : MISGEMM_FP32;
+}
+
+}  // namespace
+
+extern "C" {
+
+int misgemm_sgemm_host(char transa, char transb, int64_t m, int64_t n, int64_t k, float alpha,
+                       const float *A, int64_t lda, const float *B, int64_t ldb, float beta,
+                       float *C, int64_t ldc, int mode)
+{
+    if (mode != MISGEMM_FP32 && mode != MISGEMM_BF16X3) return -14;
+    return host_gemm<float>(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
+                            [mode](char ta, char tb, int64_t mm, int64_t nn, int64_t kk,
+                                   float al, const float *a, int64_t la, const float *b,
+                                   int64_t lb, float be, float *c, int64_t lc, void *s) {
+                                return misgemm_sgemm(ta, tb, mm, nn, kk, al, a, la, b, lb, be,
+                                                     c, lc, mode, s);
+                            });
+}
+
+int misgemm_dgemm_host(char transa, char transb, int64_t m, int64_t n, int64_t k, double alpha,
+                       const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
+                       double *C, int64_t ldc, int dmode)
+{
+    if (dmode != MISGEMM_D_FP64 && dmode != MISGEMM_D_FP32) return -14;
+    return host_gemm<double>(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
+                             [dmode](char ta, char tb, int64_t mm, int64_t nn, int64_t kk,
+                                     double al, const double *a, int64_t la, const double *b,
+                                     int64_t lb, double be, double *c, int64_t lc, void *s) {
+                                 return misgemm_dgemm(ta, tb, mm, nn, kk, al, a, la, b, lb, be,
+                                                      c, lc, dmode, s);
+                             });
+}
+
+void sgemm_(const char *transa, const char *transb, const int *m, const int *n, const int *k,
+            const float *alpha, const float *A, const int *lda, const float *B, const int *ldb,
+            const float *beta, float *C, const int *ldc)
+{
+    report("SGEMM ", misgemm_sgemm_host(*transa, *transb, *m, *n, *k, *alpha, A, *lda, B, *ldb,
+                                        *beta, C, *ldc, host_mode()));
+}
+
+void dgemm_(const char *transa, const char *transb, const int *m, const int *n, const int *k,
+            const double *alpha, const double *A, const int *lda, const double *B,
+            const int *ldb, const double *beta, double *C, const int *ldc)
+{
+    report("DGEMM ", misgemm_dgemm_host(*transa, *transb, *m, *n, *k, *alpha, A, *lda, B, *ldb,
+                                        *beta, C, *ldc, MISGEMM_D_FP64));
+}
+
+}  // extern "C"
