@@ -73,6 +73,10 @@ def _bind(lib):
                                               f64, vp, i64, vp, i64, f64, vp, i64,
                                               i64, vp, vp, vp, vp, i32]
     lib.oracle_dgemm_f128_entries.restype = i32
+    lib.oracle_getrf_f64.argtypes = [i64, vp, i64, vp, vp, i32]
+    lib.oracle_getrf_f64.restype = i32
+    lib.oracle_getrs_f64.argtypes = [i64, vp, vp, vp]
+    lib.oracle_getrs_f64.restype = i32
     lib.oracle_max_threads.argtypes = []
     lib.oracle_max_threads.restype = i32
     return lib
@@ -181,6 +185,32 @@ class Oracle:
             raise ValueError("oracle_dgemm_f128_entries failed with code %d" % rc)
         return cref, den
 
+    def getrf_f64(self, n: int, A: np.ndarray, lda: int, nthreads: int = 0):
+        """LU with partial pivoting (Section IV-C, the factorization of the
+        paper's Linpack run) of the n x n FP32 matrix, in FP64.
+
+        Returns (LU as an (n, n) float64 array [i, j], ipiv int64 (0-based
+        row swapped with row j at step j), info (0 or 1 + first zero pivot)).
+        """
+        A = _f32(A)
+        lu = np.zeros((n, n), dtype=np.float64)  # column-major storage, ld = n
+        ipiv = np.zeros(n, dtype=np.int64)
+        info = self.lib.oracle_getrf_f64(n, _ptr(A), lda, _ptr(lu), _ptr(ipiv), nthreads)
+        if info < 0:
+            raise ValueError("oracle_getrf_f64 failed with code %d" % info)
+        return lu.T, ipiv, int(info)
+
+    def getrs_f64(self, lu: np.ndarray, ipiv: np.ndarray, b: np.ndarray) -> np.ndarray:
+        """Solve A x = b from getrf_f64's factors (b is not modified)."""
+        n = lu.shape[0]
+        f = np.ascontiguousarray(np.asarray(lu, dtype=np.float64).T)  # column-major
+        piv = np.ascontiguousarray(ipiv, dtype=np.int64)
+        x = np.array(b, dtype=np.float64).reshape(-1).copy()
+        rc = self.lib.oracle_getrs_f64(n, _ptr(f), _ptr(piv), _ptr(x))
+        if rc != 0:
+            raise ValueError("oracle_getrs_f64 failed with code %d" % rc)
+        return x
+
     def sgemm_bf16x3_f64(self, transa: str, transb: str, m: int, n: int, k: int,
                          alpha: float, A: np.ndarray, lda: int, B: np.ndarray, ldb: int,
                          beta: float, C0: Optional[np.ndarray], ldc: int,
@@ -259,6 +289,27 @@ def sgemm_f64_entries(*args, **kw):
 
 def sgemm_bf16x3_f64(*args, **kw):
     return _default().sgemm_bf16x3_f64(*args, **kw)
+
+
+def getrf_f64(*args, **kw):
+    return _default().getrf_f64(*args, **kw)
+
+
+def getrs_f64(*args, **kw):
+    return _default().getrs_f64(*args, **kw)
+
+
+def hpl_scaled_residual(A: np.ndarray, x: np.ndarray, b: np.ndarray, eps: float) -> float:
+    """The residual check of the paper's Linpack run (Section IV-C, Table
+    VI): ||A x - b||_inf / (eps * (||A||_inf * ||x||_inf + ||b||_inf) * N),
+    evaluated in FP64; A is the dense (n, n) matrix."""
+    A = np.asarray(A, dtype=np.float64)
+    x = np.asarray(x, dtype=np.float64).reshape(-1)
+    b = np.asarray(b, dtype=np.float64).reshape(-1)
+    n = A.shape[0]
+    r = np.max(np.abs(A @ x - b))
+    norm_a = np.max(np.sum(np.abs(A), axis=1))
+    return float(r / (eps * (norm_a * np.max(np.abs(x)) + np.max(np.abs(b))) * n))
 
 
 def dgemm_f128(*args, **kw):

@@ -33,6 +33,13 @@
  * binary128 in ascending p, alpha and beta are applied after the sum, and
  * the result is rounded once to FP64.
  *
+ * The LU functions restate the factorization behind the paper's Linpack
+ * run (Section IV-C, HPL): P A = L U with partial pivoting, by the textbook
+ * right-looking elimination in FP64 (column j: pick the row of largest
+ * magnitude at or below the diagonal, first one on ties; swap it up; divide
+ * the column below the diagonal by the pivot; subtract the outer product
+ * from the trailing matrix), and the triangular solves that use it.
+ *
  * Build: gcc -O2 -fopenmp -ffp-contract=off -fPIC -shared (no -ffast-math).
  */
 #include <math.h>
@@ -430,5 +437,74 @@ int oracle_dgemm_f128_entries(char transa, char transb, int64_t m, int64_t n, in
     for (int64_t e = 0; e < count; ++e)
         dgemm_entry(ta, tb, k, alpha, A, lda, B, ldb, beta, C0, ldc, use_ab, rows[e], cols[e],
                     &cref[e], &den[e]);
+    return ORACLE_OK;
+}
+
+/* ------------------------------------------------------------------------
+ * LU factorization with partial pivoting (Section IV-C), FP64.
+ * ------------------------------------------------------------------------ */
+
+/*
+ * A (n x n FP32, leading dimension lda) is read; LU (n x n FP64, leading
+ * dimension n) receives L (unit diagonal not stored) below the diagonal and
+ * U on and above it; ipiv[j] is the row swapped with row j at step j
+ * (0-based).  Returns 0, or 1 + the first j whose pivot is zero (the
+ * elimination then continues without dividing that column), or
+ * ORACLE_BAD_ARG.
+ */
+int oracle_getrf_f64(int64_t n, const float *A, int64_t lda, double *LU, int64_t *ipiv,
+                     int nthreads)
+{
+    if (n < 0 || lda < (n > 0 ? n : 1)) return ORACLE_BAD_ARG;
+    set_threads(nthreads);
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t i = 0; i < n; ++i) LU[i + j * n] = (double)A[i + j * lda];
+    int info = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        int64_t p = j;
+        double best = fabs(LU[j + j * n]);
+        for (int64_t i = j + 1; i < n; ++i)
+            if (fabs(LU[i + j * n]) > best) { best = fabs(LU[i + j * n]); p = i; }
+        ipiv[j] = p;
+        if (p != j)
+            for (int64_t c = 0; c < n; ++c) {
+                double t = LU[j + c * n];
+                LU[j + c * n] = LU[p + c * n];
+                LU[p + c * n] = t;
+            }
+        const double piv = LU[j + j * n];
+        if (piv == 0.0) {
+            if (info == 0) info = (int)(j + 1);
+            continue;
+        }
+        for (int64_t i = j + 1; i < n; ++i) LU[i + j * n] /= piv;
+#pragma omp parallel for schedule(static)
+        for (int64_t c = j + 1; c < n; ++c) {
+            const double u = LU[j + c * n];
+            for (int64_t i = j + 1; i < n; ++i) LU[i + c * n] -= LU[i + j * n] * u;
+        }
+    }
+    return info;
+}
+
+/*
+ * Solve A x = b with the factors of oracle_getrf_f64: apply the row swaps to
+ * b, then L y = b (forward, unit diagonal), then U x = y (backward).  b (n
+ * FP64) is overwritten with x.
+ */
+int oracle_getrs_f64(int64_t n, const double *LU, const int64_t *ipiv, double *b)
+{
+    if (n < 0) return ORACLE_BAD_ARG;
+    for (int64_t j = 0; j < n; ++j) {
+        const int64_t p = ipiv[j];
+        if (p < 0 || p >= n) return ORACLE_BAD_ARG;
+        if (p != j) { double t = b[j]; b[j] = b[p]; b[p] = t; }
+    }
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t c = 0; c < i; ++c) b[i] -= LU[i + c * n] * b[c];
+    for (int64_t i = n - 1; i >= 0; --i) {
+        for (int64_t c = i + 1; c < n; ++c) b[i] -= LU[i + c * n] * b[c];
+        b[i] /= LU[i + i * n];
+    }
     return ORACLE_OK;
 }

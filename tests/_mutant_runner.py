@@ -12,7 +12,7 @@ from tests import pins  # noqa: E402
 
 def main(path):
     o = oracle.Oracle(path)
-    pin_set = pins.ALL_SGEMM_PINS + pins.ALL_DGEMM_PINS + [
+    pin_set = pins.ALL_SGEMM_PINS + pins.ALL_DGEMM_PINS + pins.ALL_LU_PINS + [
         lambda o: pins.pin_bf16_rne_vs_torch(o, count=1 << 16),
         lambda o: pins.pin_bf16x3_exhaustive(o, 0x3F800000, 0x3F800000 + (1 << 22)),
         pins.pin_bf16x3_method,

@@ -458,3 +458,97 @@ def pin_dgemm_transpose_and_entries(o):
 ALL_DGEMM_PINS = [pin_dgemm_fraction_bruteforce, pin_dgemm_cancellation, pin_dgemm_numpy,
                   pin_dgemm_integer_regime, pin_dgemm_identity_and_degenerate,
                   pin_dgemm_transpose_and_entries]
+
+
+# ---------------------------------------------------------------------------
+# LU with partial pivoting (the factorization of the paper's Linpack run,
+# Section IV-C): against LAPACK through scipy, exact rational elimination,
+# the reconstruction P A = L U, ties, zero pivots and exact solves.
+# ---------------------------------------------------------------------------
+
+def _lu_fraction(a):
+    """Textbook elimination with partial pivoting in exact rationals."""
+    n = len(a)
+    m = [[Fraction(float(v)) for v in row] for row in a]
+    piv = []
+    for j in range(n):
+        p = max(range(j, n), key=lambda i: (abs(m[i][j]), -i))
+        piv.append(p)
+        m[j], m[p] = m[p], m[j]
+        if m[j][j] == 0:
+            continue
+        for i in range(j + 1, n):
+            m[i][j] /= m[j][j]
+            for c in range(j + 1, n):
+                m[i][c] -= m[i][j] * m[j][c]
+    return m, piv
+
+
+def pin_lu_lapack(o):
+    """Same pivots as LAPACK's dgetrf (scipy.linalg.lu_factor), factors
+    equal to FP64 rounding."""
+    import scipy.linalg as sl
+    rng = np.random.default_rng(41)
+    for n in (1, 2, 7, 64, 129):
+        a = rng.uniform(-1, 1, (n, n)).astype(np.float32)
+        lu, piv, info = o.getrf_f64(n, a.reshape(-1, order="F"), n)
+        lu2, piv2 = sl.lu_factor(a.astype(np.float64))
+        assert info == 0 and np.array_equal(piv, piv2), n
+        assert np.max(np.abs(lu - lu2)) <= 1e-12 * max(1.0, np.max(np.abs(lu2))), n
+
+
+def pin_lu_fraction(o):
+    """Exact rational elimination on small integer matrices: identical
+    pivots, factors within a few FP64 ulps."""
+    rng = np.random.default_rng(42)
+    for n in (2, 3, 5, 6):
+        for _ in range(3):
+            a = rng.integers(-9, 10, (n, n)).astype(np.float32)
+            m, piv = _lu_fraction(a)
+            lu, ipiv, info = o.getrf_f64(n, a.reshape(-1, order="F"), n)
+            assert list(ipiv) == piv
+            for i in range(n):
+                for j in range(n):
+                    want = float(m[i][j])
+                    assert abs(lu[i, j] - want) <= 8 * np.spacing(max(abs(want), 1e-300)), (n, i, j)
+
+
+def pin_lu_reconstruct_ties_singular(o):
+    """P A = L U to FP64 roundoff; the first of equal magnitudes is the
+    pivot; a zero column reports its 1-based index and leaves the rest
+    factored."""
+    rng = np.random.default_rng(43)
+    n = 40
+    a = rng.standard_normal((n, n)).astype(np.float32)
+    lu, ipiv, info = o.getrf_f64(n, a.reshape(-1, order="F"), n)
+    L = np.tril(lu, -1) + np.eye(n)
+    U = np.triu(lu)
+    pa = a.astype(np.float64).copy()
+    for j, p in enumerate(ipiv):
+        pa[[j, p]] = pa[[p, j]]
+    assert np.max(np.abs(L @ U - pa)) <= n * 2.0 ** -50 * np.max(np.abs(a))
+    t = np.array([[1, 2, 0], [-1, 3, 1], [1, 1, 2]], dtype=np.float32)
+    _, ipiv, info = o.getrf_f64(3, t.reshape(-1, order="F"), 3)
+    assert ipiv[0] == 0 and info == 0
+    s = np.array([[2, 0, 1], [4, 0, 3], [1, 0, 5]], dtype=np.float32)  # zero column 1
+    _, _, info = o.getrf_f64(3, s.reshape(-1, order="F"), 3)
+    assert info == 2
+
+
+def pin_lu_exact_solve(o):
+    """A = P T with T upper triangular, power-of-two entries: the solve
+    reproduces the integer solution exactly."""
+    rng = np.random.default_rng(44)
+    n = 12
+    t = np.triu(2.0 ** rng.integers(-3, 4, (n, n))) * rng.choice([-1.0, 1.0], (n, n))
+    t += np.eye(n) * 64.0
+    p = np.eye(n)[rng.permutation(n)]
+    a = (p @ t).astype(np.float32)
+    x = rng.integers(-5, 6, n).astype(np.float64)
+    b = a.astype(np.float64) @ x
+    lu, ipiv, info = o.getrf_f64(n, a.reshape(-1, order="F"), n)
+    assert np.array_equal(o.getrs_f64(lu, ipiv, b), x)
+
+
+ALL_LU_PINS = [pin_lu_lapack, pin_lu_fraction, pin_lu_reconstruct_ties_singular,
+               pin_lu_exact_solve]

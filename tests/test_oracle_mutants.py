@@ -42,6 +42,12 @@ MUTANTS = [
      "    return trans ? X[i + p * ld] : X[p + i * ld];"),
     ("dgemm-dropped-beta-term", "        c += (quad)beta * c0;\n", ""),
     ("dgemm-alpha-on-den-only", "    quad c = (quad)alpha * s;", "    quad c = s;"),
+    ("lu-last-pivot-on-ties", "            if (fabs(LU[i + j * n]) > best) {",
+     "            if (fabs(LU[i + j * n]) >= best) {"),
+    ("lu-swap-skips-L-part", "            for (int64_t c = 0; c < n; ++c) {\n                double t = LU[j + c * n];",
+     "            for (int64_t c = j; c < n; ++c) {\n                double t = LU[j + c * n];"),
+    ("lu-update-skips-last-row", "            for (int64_t i = j + 1; i < n; ++i) LU[i + c * n] -= LU[i + j * n] * u;",
+     "            for (int64_t i = j + 1; i + 1 < n; ++i) LU[i + c * n] -= LU[i + j * n] * u;"),
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))

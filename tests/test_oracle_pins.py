@@ -22,6 +22,20 @@ def test_dgemm_pin(o, pin):
     pin(o)
 
 
+@pytest.mark.parametrize("pin", pins.ALL_LU_PINS, ids=lambda f: f.__name__)
+def test_lu_pin(o, pin):
+    pin(o)
+
+
+def test_hpl_residual_formula():
+    """The residual of Table VI on a case worked by hand: A = 2 I (n = 2),
+    x = (1, 1), b = (2, 2.5): ||Ax - b|| = 0.5, ||A|| = 2, ||x|| = 1,
+    ||b|| = 2.5, so 0.5 / (eps * (2 + 2.5) * 2)."""
+    eps = 2.0 ** -24
+    r = oracle.hpl_scaled_residual(2 * np.eye(2), [1.0, 1.0], [2.0, 2.5], eps)
+    assert r == 0.5 / (eps * 4.5 * 2)
+
+
 def test_dgemm_bounds():
     assert oracle.tol_d(4096) == 2 * 4096 * 2.0 ** -53
     assert oracle.tol_d(2) == 5 * 2.0 ** -53
