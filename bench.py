@@ -44,7 +44,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="square",
                     choices=["square", "c1", "rankk", "wide", "batch", "dominant", "peak",
-                             "dgemm", "host"],
+                             "dgemm", "host", "lu"],
                     help="dominant: only the 8192^3 NN problem of the square sweep in both "
                          "forms plus a 1 GiB device copy, for counter collection")
     ap.add_argument("--no-cpu-baseline", action="store_true",
@@ -659,6 +659,68 @@ def host_line(args, torch, mg):
             "rows": rows}
 
 
+def lu_line(args, torch, mg):
+    """The Linpack workload of the paper (Section IV-C): LU with partial
+    pivoting of an N x N uniform[-1,1] matrix and the solve of A x = b, at
+    the paper's N = 4608 and at N = 16384, trailing updates in both sgemm
+    forms; GFLOP/s by the HPL count (2/3 N^3 + 3/2 N^2) / t, and the scaled
+    residual of Table VI (with FP32's eps, and with the 2^-53 the paper's
+    double-precision HPL used)."""
+    import oracle
+    dev = torch.device("cuda:0")
+    rows = []
+    for n in (4608, 16384):
+        rng = np.random.default_rng(4608 + n)
+        a = rng.uniform(-1, 1, (n, n)).astype(np.float32)
+        b = rng.uniform(-1, 1, n).astype(np.float32)
+        a_cm = torch.from_numpy(np.ascontiguousarray(a.T).reshape(-1)).to(dev)
+        for mode, name in ((mg.FP32, "fp32"), (mg.BF16X3, "bf16x3")):
+            times = []
+            for rep_ in range(args.warmup + max(1, min(args.steps, 3))):
+                A = a_cm.clone()
+                ipiv = torch.empty(n, dtype=torch.int64, device=dev)
+                info = torch.empty(1, dtype=torch.int32, device=dev)
+                B = torch.from_numpy(b.copy()).to(dev)
+                torch.cuda.synchronize()
+                s_ = torch.cuda.Event(enable_timing=True)
+                m_ = torch.cuda.Event(enable_timing=True)
+                e_ = torch.cuda.Event(enable_timing=True)
+                s_.record()
+                mg.sgetrf(n, A, n, ipiv, info, mode)
+                m_.record()
+                mg.sgetrs(n, 1, A, n, ipiv, B, n, mode)
+                e_.record()
+                torch.cuda.synchronize()
+                if rep_ >= args.warmup:
+                    times.append((s_.elapsed_time(m_), m_.elapsed_time(e_)))
+            t_f = min(t[0] for t in times) * 1e-3
+            t_s = min(t[1] for t in times) * 1e-3
+            x = B.cpu().numpy().astype(np.float64)
+            hpl_flops = 2.0 / 3.0 * n ** 3 + 1.5 * n ** 2
+            rows.append({"n": n, "form": name, "info": int(info.item()),
+                         "getrf_ms": round(t_f * 1e3, 3), "getrs_ms": round(t_s * 1e3, 3),
+                         "gflops": round(hpl_flops / (t_f + t_s) / 1e9, 1),
+                         "scaled_residual_eps32": oracle.hpl_scaled_residual(a, x, b, 2.0 ** -24),
+                         "scaled_residual_eps64": oracle.hpl_scaled_residual(a, x, b, 2.0 ** -53)})
+            del A, B
+        del a_cm
+    line = {"workload": "LU with partial pivoting + solve (HPL-style), uniform[-1,1]",
+            "rows": rows,
+            "paper": "Parallella, N=4608, NB=768: 0.495 GFLOP/s, scaled residual 2.11e10 "
+                     "(eps 2^-53), Table VI"}
+    if not args.no_cpu_baseline:
+        cores = len(os.sched_getaffinity(0))
+        n = 2048
+        a = np.random.default_rng(7).uniform(-1, 1, (n, n)).astype(np.float32)
+        t0 = time.perf_counter()
+        oracle.getrf_f64(n, np.ascontiguousarray(a.T).reshape(-1), n, nthreads=cores)
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": (2.0 / 3.0 * n ** 3) / dt / 1e9, "unit": "GFLOP/s",
+                                "cores": cores, "kind": "oracle",
+                                "sample": "FP64 textbook LU of one 2048 x 2048 matrix"}
+    return line
+
+
 COPY_BYTES = 1 << 30
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sgemm_dominant8192_hbm_counters.txt")
 # what decides the sgemm kernels and which of them runs: their sources and
@@ -730,6 +792,9 @@ def main():
         return
     if args.workload == "dominant":
         dominant_only(args, torch, mg)
+        return
+    if args.workload == "lu":
+        print(json.dumps(lu_line(args, torch, mg)))
         return
     if args.workload == "host":
         print(json.dumps(host_line(args, torch, mg)))

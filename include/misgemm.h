@@ -232,6 +232,36 @@ int misgemm_dgemm(char transa, char transb, int64_t m, int64_t n, int64_t k,
                   int dmode, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * LU with partial pivoting and the solve: the Linpack (HPL) workload of the
+ * paper's Section IV-C, on the sgemm path.
+ * ------------------------------------------------------------------------- */
+
+/*
+ * P A = L U for the n x n FP32 matrix A (device, column-major, lda >= n),
+ * overwritten by L (unit diagonal not stored) and U.  ipiv (device, n
+ * int64): row ipiv[j] (0-based, >= j) was swapped with row j at step j,
+ * first row of largest magnitude on ties.  info (device int): 0, or 1 + the
+ * first j with a zero pivot (the factorization then completes without
+ * dividing that column, as LAPACK's getrf does).  Recursive right-looking
+ * algorithm: the trailing updates and the off-diagonal parts of the
+ * triangular solves are sgemm calls in `mode` (MISGEMM_FP32 or
+ * MISGEMM_BF16X3); 32-column leaf panels are factored by one workgroup.
+ * Asynchronous on `stream`; uses the library scratch of misgemm_sgemm.
+ * Errors: -1 n, -2 A, -3 lda, -4 ipiv, -5 info, -6 mode (before any launch).
+ */
+int misgemm_sgetrf(int64_t n, float *A, int64_t lda, int64_t *ipiv, int *info, int mode,
+                   void *stream);
+
+/*
+ * Solve A X = B with the factors of misgemm_sgetrf: B (n x nrhs, device,
+ * ldb >= n) is overwritten with X (row swaps, then L, then U; the
+ * off-diagonal blocks through sgemm in `mode`).  Errors: -1 n, -2 nrhs,
+ * -3 A, -4 lda, -5 ipiv, -6 B, -7 ldb, -8 mode.
+ */
+int misgemm_sgetrs(int64_t n, int64_t nrhs, const float *A, int64_t lda, const int64_t *ipiv,
+                   float *B, int64_t ldb, int mode, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Host-pointer BLAS: for callers whose matrices live in host memory, as the
  * paper's library served unmodified BLAS users (Sections III-A, III-C).
  * ------------------------------------------------------------------------- */

@@ -90,6 +90,10 @@ def _load():
     lib.misgemm_dgemm_host.argtypes = [c, c, i64, i64, i64, f64, vp, i64, vp, i64, f64, vp, i64,
                                        i32]
     lib.misgemm_dgemm_host.restype = i32
+    lib.misgemm_sgetrf.argtypes = [i64, vp, i64, vp, vp, i32, vp]
+    lib.misgemm_sgetrf.restype = i32
+    lib.misgemm_sgetrs.argtypes = [i64, i64, vp, i64, vp, vp, i64, i32, vp]
+    lib.misgemm_sgetrs.restype = i32
     lib.misgemm_sgemm_split.argtypes = sig + [i32, i32, i32, vp]
     lib.misgemm_sgemm_split.restype = i32
     lib.misgemm_sgemm_ws.argtypes = sig + [vp, i64, vp]
@@ -221,6 +225,21 @@ def dgemm_host(transa: str, transb: str, m: int, n: int, k: int, alpha: float, A
                                     _host_ptr(A, np.float64), lda, _host_ptr(B, np.float64), ldb,
                                     float(beta), _host_ptr(C, np.float64), ldc, int(dmode))
     _check(rc, "misgemm_dgemm_host")
+
+
+def sgetrf(n: int, A, lda: int, ipiv, info, mode=FP32, stream=None) -> None:
+    """LU with partial pivoting of the n x n float32 device matrix A (in
+    place); ipiv an int64 device tensor of n, info an int32 device tensor."""
+    rc = _load().misgemm_sgetrf(n, _ptr(A), lda, _ptr(ipiv), _ptr(info), _mode(mode),
+                                _stream(stream))
+    _check(rc, "misgemm_sgetrf")
+
+
+def sgetrs(n: int, nrhs: int, A, lda: int, ipiv, B, ldb: int, mode=FP32, stream=None) -> None:
+    """Solve A X = B (B overwritten) with the factors of sgetrf."""
+    rc = _load().misgemm_sgetrs(n, nrhs, _ptr(A), lda, _ptr(ipiv), _ptr(B), ldb, _mode(mode),
+                                _stream(stream))
+    _check(rc, "misgemm_sgetrs")
 
 
 def sgemm_split(transa: str, transb: str, m: int, n: int, k: int, alpha: float, A, lda: int,

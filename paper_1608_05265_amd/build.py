@@ -24,7 +24,7 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-I" + os.path.join(os.path.dirname(HERE), "include")]
 
 SOURCES = ["api.cpp", "aux_kernels.hip", "sgemm_f32.hip", "sgemm_x3.hip", "sgemm_x3k.hip",
-           "dgemm.hip", "host_blas.cpp"]
+           "dgemm.hip", "host_blas.cpp", "lu.hip"]
 # measurement helper (matrix-core rate probe), a library of its own
 PROBE_SOURCE = "probe_mfma.hip"
 PROBE_LIB = os.path.join(HERE, "libmisgemm_probe.so")

@@ -107,6 +107,17 @@ def test_quick_returns_need_no_device(mg):
     assert lib.misgemm_dgemm(*dargs, 7, None) == -14
     assert lib.misgemm_dgemm(b"N", b"N", 0, 5, 5, 1.0, None, 1, None, 5, 0.0, None, 1, 0,
                              None) == 0
+    # LU and solve: argument positions checked before any launch
+    assert lib.misgemm_sgetrf(-1, None, 1, None, None, 0, None) == -1
+    assert lib.misgemm_sgetrf(4, None, 4, 0x2000, 0x3000, 0, None) == -2
+    assert lib.misgemm_sgetrf(4, 0x1000, 3, 0x2000, 0x3000, 0, None) == -3
+    assert lib.misgemm_sgetrf(4, 0x1000, 4, None, 0x3000, 0, None) == -4
+    assert lib.misgemm_sgetrf(4, 0x1000, 4, 0x2000, None, 0, None) == -5
+    assert lib.misgemm_sgetrf(4, 0x1000, 4, 0x2000, 0x3000, 9, None) == -6
+    assert lib.misgemm_sgetrs(4, -1, 0x1000, 4, 0x2000, 0x3000, 4, 0, None) == -2
+    assert lib.misgemm_sgetrs(4, 1, 0x1000, 4, 0x2000, 0x3000, 3, 0, None) == -7
+    assert lib.misgemm_sgetrs(4, 1, 0x1000, 4, 0x2000, 0x3000, 4, 5, None) == -8
+    assert lib.misgemm_sgetrs(0, 1, None, 1, None, None, 1, 0, None) == 0
     assert lib.misgemm_bf16x3_split(None, 0, None, None) == 0
     assert lib.misgemm_bf16x3_split(None, 3, None, None) == -1
     assert lib.misgemm_batch_launch(None, None) == 1005

@@ -1,0 +1,133 @@
+"""LU with partial pivoting and the solve (the Linpack workload of the
+paper's Section IV-C) on the sgemm path, against the FP64 oracle: identical
+pivots and factors where the pivot choice is unique, exact results on data
+that factors exactly, and for general random matrices (where rounding may
+legitimately pick another of two nearly equal pivots) valid pivots, the
+backward error of P A = L U, bounded multipliers and the HPL scaled
+residual of the solve."""
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+EPS32 = 2.0 ** -24
+
+
+def _mg():
+    import paper_1608_05265_amd as mg
+    return mg
+
+
+def _factor(a, mode, lda=None):
+    """GPU sgetrf of the dense float32 matrix a; returns (LU dense, ipiv, info)."""
+    import torch
+    mg = _mg()
+    n = a.shape[0]
+    lda = lda or n
+    buf = np.zeros((n, lda), dtype=np.float32)  # column-major storage with padding rows
+    buf[:, :n] = a.T
+    d = torch.device("cuda:0")
+    A = torch.from_numpy(buf.reshape(-1).copy()).to(d)
+    ipiv = torch.zeros(max(n, 1), dtype=torch.int64, device=d)
+    info = torch.zeros(1, dtype=torch.int32, device=d)
+    mg.sgetrf(n, A, lda, ipiv, info, mode)
+    torch.cuda.synchronize()
+    lu = A.cpu().numpy().reshape(n, lda)[:, :n].T
+    pad = A.cpu().numpy().reshape(n, lda)[:, n:]
+    assert np.array_equal(pad, buf[:, n:]), "padding rows written"
+    return lu.astype(np.float64), ipiv.cpu().numpy()[:n], int(info.item()), A, ipiv
+
+
+def _solve(A, ipiv, n, b, mode):
+    import torch
+    mg = _mg()
+    B = torch.from_numpy(np.asarray(b, dtype=np.float32).copy()).to(A.device)
+    mg.sgetrs(n, 1, A, n, ipiv, B, n, mode)
+    torch.cuda.synchronize()
+    return B.cpu().numpy().astype(np.float64)
+
+
+def _permuted(a, ipiv):
+    pa = np.array(a, dtype=np.float64)
+    for j, p in enumerate(ipiv):
+        pa[[j, p]] = pa[[p, j]]
+    return pa
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["fp32", "bf16x3"])
+def test_lu_unique_pivots_match_oracle(mode):
+    """Permuted diagonally dominant matrices: every pivot is unique by a wide
+    margin, so the GPU pivots equal the oracle's and the factors agree to
+    FP32 accuracy; sizes around the 32-column leaf and with several levels."""
+    rng = np.random.default_rng(50)
+    for n in (1, 31, 32, 33, 100, 257):
+        d = rng.uniform(-1, 1, (n, n)) + np.diag(rng.uniform(n, 2 * n, n))
+        a = d[rng.permutation(n)].astype(np.float32)
+        lu, ipiv, info = _factor(a, mode)[:3]
+        lu_o, ipiv_o, info_o = oracle.getrf_f64(n, a.T.reshape(-1), n)
+        assert info == 0 and info_o == 0
+        assert np.array_equal(ipiv, ipiv_o), n
+        scale = np.max(np.abs(lu_o))
+        assert np.max(np.abs(lu - lu_o)) <= 8 * n * EPS32 * scale, n
+
+
+def test_lu_exact_data_is_exact():
+    """A = P T with T upper triangular and power-of-two entries: every
+    operation of the factorization and the solve is exact."""
+    rng = np.random.default_rng(51)
+    n = 96
+    t = np.triu(2.0 ** rng.integers(-3, 4, (n, n))) * rng.choice([-1.0, 1.0], (n, n))
+    t += np.eye(n) * 256.0
+    a = (np.eye(n)[rng.permutation(n)] @ t).astype(np.float32)
+    lu, ipiv, info, A, dpiv = _factor(a, 0)
+    lu_o, ipiv_o, _ = oracle.getrf_f64(n, a.T.reshape(-1), n)
+    assert np.array_equal(ipiv, ipiv_o) and np.array_equal(lu, lu_o)
+    x = rng.integers(-5, 6, n).astype(np.float64)
+    b = a.astype(np.float64) @ x
+    assert np.array_equal(_solve(A, dpiv, n, b, 0), x)
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["fp32", "bf16x3"])
+def test_lu_random_backward_error_and_residual(mode):
+    """Random uniform[-1,1] matrices (the HPL generator's distribution):
+    valid pivots, |L| <= 1, ||P A - L U|| small against n eps ||L|| ||U||,
+    and the solve passes HPL's check (scaled residual < 16 with FP32 eps)."""
+    rng = np.random.default_rng(52)
+    for n in (200, 1000, 2048):
+        a = rng.uniform(-1, 1, (n, n)).astype(np.float32)
+        lu, ipiv, info, A, dpiv = _factor(a, mode, lda=n + 5 if n == 200 else None)
+        assert info == 0
+        assert np.all(ipiv >= np.arange(n)) and np.all(ipiv < n)
+        L = np.tril(lu, -1) + np.eye(n)
+        U = np.triu(lu)
+        assert np.max(np.abs(L)) <= 1.0 + 1e-6
+        err = np.max(np.abs(_permuted(a, ipiv) - L @ U))
+        bound = 4 * n * EPS32 * np.max(np.sum(np.abs(L), 1)) * np.max(np.sum(np.abs(U), 0))
+        assert err <= bound, (n, err, bound)
+        if n == 200:
+            continue  # padded lda: solve takes ld = n
+        b = rng.uniform(-1, 1, n)
+        x = _solve(A, dpiv, n, b.astype(np.float32), mode)
+        r = oracle.hpl_scaled_residual(a, x, b.astype(np.float32), EPS32)
+        assert r < 16.0, (n, r)
+
+
+def test_lu_singular_and_errors():
+    """A zero column: info names it (1-based) and the rest is factored; a
+    zero matrix reports column 1; n = 0 clears info."""
+    import torch
+    mg = _mg()
+    rng = np.random.default_rng(53)
+    n = 70
+    a = rng.uniform(-1, 1, (n, n)).astype(np.float32)
+    a[:, 40] = 0.0
+    lu, ipiv, info = _factor(a, 0)[:3]
+    assert info == 41
+    assert _factor(np.zeros((5, 5), np.float32), 0)[2] == 1
+    # n = 0: nothing to factor; info still cleared
+    info_t = torch.full((1,), 7, dtype=torch.int32, device="cuda")
+    mg.sgetrf(0, None, 1, None, info_t, 0)
+    torch.cuda.synchronize()
+    assert int(info_t.item()) == 0
