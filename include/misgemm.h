@@ -245,7 +245,9 @@ int misgemm_dgemm(char transa, char transb, int64_t m, int64_t n, int64_t k,
  * dividing that column, as LAPACK's getrf does).  Recursive right-looking
  * algorithm: the trailing updates and the off-diagonal parts of the
  * triangular solves are sgemm calls in `mode` (MISGEMM_FP32 or
- * MISGEMM_BF16X3); 32-column leaf panels are factored by one workgroup.
+ * MISGEMM_BF16X3); leaf panels of 8 columns (4 when taller than 8192 rows)
+ * are factored by one workgroup, and each leaf's interchanges are applied
+ * to the rest of the matrix right after it.
  * Asynchronous on `stream`; uses the library scratch of misgemm_sgemm.
  * Errors: -1 n, -2 A, -3 lda, -4 ipiv, -5 info, -6 mode (before any launch).
  */
@@ -255,8 +257,10 @@ int misgemm_sgetrf(int64_t n, float *A, int64_t lda, int64_t *ipiv, int *info, i
 /*
  * Solve A X = B with the factors of misgemm_sgetrf: B (n x nrhs, device,
  * ldb >= n) is overwritten with X (row swaps, then L, then U; the
- * off-diagonal blocks through sgemm in `mode`).  Errors: -1 n, -2 nrhs,
- * -3 A, -4 lda, -5 ipiv, -6 B, -7 ldb, -8 mode.
+ * off-diagonal blocks through sgemm in `mode`).  The swaps exchange rows k
+ * and ipiv[k] for k = 0 .. n-1 in order, whatever ipiv holds; an entry
+ * outside [0, n) is skipped (no access out of bounds).  Errors: -1 n,
+ * -2 nrhs, -3 A, -4 lda, -5 ipiv, -6 B, -7 ldb, -8 mode.
  */
 int misgemm_sgetrs(int64_t n, int64_t nrhs, const float *A, int64_t lda, const int64_t *ipiv,
                    float *B, int64_t ldb, int mode, void *stream);

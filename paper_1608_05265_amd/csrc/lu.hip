@@ -2,11 +2,15 @@
 // Linpack (HPL) workload of the paper's Section IV-C, on the sgemm path.
 //
 // Recursive right-looking LU: factor the left half of the column range,
-// swap its pivots into the right half, L11^{-1} A12 (recursive triangular
-// solve), A22 -= A21 A12 (one sgemm -- the rank-k trailing update), factor
-// A22, swap its pivots back into the left half.  Almost all flops land in
-// sgemm calls of decreasing size; the leaves are 32-column panels that one
-// workgroup factors column by column.
+// L11^{-1} A12 (recursive triangular solve), A22 -= A21 A12 (one sgemm --
+// the rank-k trailing update), factor A22.  Almost all flops land in sgemm
+// calls of decreasing size.  The leaves are narrow panels (8 columns, 4 or
+// 2 when the panel is taller than 8192 or 16384 rows) that one workgroup
+// factors with the panel held in registers; each leaf's row interchanges
+// are applied to every other column of the matrix right after it, which
+// gives the same result as swapping at each level of the recursion (a
+// column receives the interchanges in pivot order either way, and the
+// columns right of a range are not touched before its left half is done).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -14,24 +18,184 @@
 
 namespace {
 
-constexpr int LEAF = 32;       // columns of a leaf panel / rows of a leaf solve
-constexpr int LEAF_THREADS = 1024;
+constexpr int LEAF = 32;            // rows of a leaf triangular solve
+constexpr int PANEL_LEAF = 8;       // columns of a leaf panel
+constexpr int LEAF_THREADS = 1024;  // threads of the leaf-panel workgroup
+constexpr int LEAF_WAVES = LEAF_THREADS / 64;
+constexpr int LEAF_REGS = 64;       // panel values one thread holds
+constexpr int SWAP_BLOCK = 32;      // interchanges composed into one permutation
+constexpr int SWAP_THREADS = 256;   // laswp workgroup: four wavefronts
+constexpr int SWAP_COLS_PER_WAVE = 16;
 
-// Factor the m x w panel P (w <= LEAF, leading dimension lda; its top-left
-// element is A(row0, row0)): for each column j, the row of largest
-// magnitude at or below j (first one on ties) is swapped up across the
-// panel, the column below the diagonal is divided by the pivot, and the
-// outer product is subtracted from the panel's remaining columns.  A zero
-// pivot leaves its column as it is and records row0 + j + 1 in *info if no
-// earlier zero pivot did.  ipiv receives global row indices.
+// Pivot search key: the magnitude's bits above the complemented row index.
+// Magnitudes are non-negative, so their bit patterns order as the values
+// do, and the largest key is the largest magnitude at the lowest row -- the
+// first row of largest magnitude, as a sequential scan finds it.  0 means
+// "no candidate" (a row whose magnitude is NaN is never one).
+__device__ inline uint64_t pivot_key(float mag, int row)
+{
+    return ((uint64_t)__float_as_uint(mag) << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)row);
+}
+
+__device__ inline uint64_t umax64(uint64_t a, uint64_t b) { return a > b ? a : b; }
+
+// v from another lane of the same 16-lane row (DPP control CTRL).
+template <int CTRL>
+__device__ inline uint64_t dpp64(uint64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, 0xF, 0xF, true);
+    const uint32_t hi =
+        (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTRL, 0xF, 0xF, true);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ inline uint64_t readlane64(uint64_t v, int lane)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Maximum over each 16-lane row, left in every lane of the row: exchange
+// with the neighbour (quad_perm 1,0,3,2), the other pair (quad_perm
+// 2,3,0,1), the mirrored quad in the half row, the mirrored half row.
+__device__ inline uint64_t row_max_key(uint64_t k)
+{
+    k = umax64(k, dpp64<0xB1>(k));
+    k = umax64(k, dpp64<0x4E>(k));
+    k = umax64(k, dpp64<0x141>(k));
+    k = umax64(k, dpp64<0x140>(k));
+    return k;
+}
+
+// Maximum over the wavefront (all lanes active), uniform.
+__device__ inline uint64_t wave_max_key(uint64_t k)
+{
+    k = row_max_key(k);
+    return umax64(umax64(readlane64(k, 0), readlane64(k, 16)),
+                  umax64(readlane64(k, 32), readlane64(k, 48)));
+}
+
+// Factor the m x w panel P (w <= W, m <= RPT * LEAF_THREADS, leading
+// dimension lda; its top-left element is A(row0, row0)).  Thread t holds
+// rows t, t + LEAF_THREADS, ... of the panel in registers.  For each column
+// j: the row of largest magnitude at or below j (first one on ties) is
+// exchanged with row j across the panel, the column below the diagonal is
+// divided by the pivot, and the outer product is subtracted from the
+// remaining columns.  A zero pivot leaves its column as it is and records
+// row0 + j + 1 in *info if no earlier zero pivot did.  ipiv receives
+// global row indices.  Two barriers per column: one after the per-wave
+// maxima are posted, one after the two exchanged rows are posted.
+template <int RPT, int W>
 __global__ __launch_bounds__(LEAF_THREADS) void lu_leaf_kernel(float *__restrict__ P,
-                                                              int64_t lda, int64_t m, int w,
+                                                              int64_t lda, int m, int w,
                                                               int64_t *__restrict__ ipiv,
                                                               int64_t row0, int *__restrict__ info)
 {
+    static_assert(RPT * W <= LEAF_REGS, "panel does not fit the register budget");
+    static_assert(LEAF_WAVES <= 16, "per-wave maxima are combined in one 16-lane row");
+    __shared__ uint64_t wkey[LEAF_WAVES];
+    __shared__ float prow[W], jrow[W];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    float v[RPT][W];
+#pragma unroll
+    for (int c = 0; c < W; ++c) {
+        const float *pc = P + (int64_t)c * lda;  // uniform column base, 32-bit row offsets
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+            const uint32_t r = (uint32_t)(t + i * LEAF_THREADS);
+            v[i][c] = (r < (uint32_t)m && c < w) ? pc[r] : 0.0f;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        if (j >= w) break;
+        uint64_t key = 0;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+            const int r = t + i * LEAF_THREADS;
+            const float a = fabsf(v[i][j]);
+            const bool cand = r >= j && r < m && !__builtin_isnan(a);
+            key = umax64(key, cand ? pivot_key(a, r) : 0);
+        }
+        key = wave_max_key(key);
+        if (lane == 0) wkey[wave] = key;
+        __syncthreads();
+        key = row_max_key(lane < LEAF_WAVES ? wkey[lane] : 0);
+        key = readlane64(key, 0);
+        const int idx = key == 0 ? -1 : (int)(0xFFFFFFFFu - (uint32_t)key);
+        const float pivot_mag = key == 0 ? -1.0f : __uint_as_float((uint32_t)(key >> 32));
+        const int p = idx >= 0 ? idx : j;
+        const int pt = p % LEAF_THREADS, pi = p / LEAF_THREADS;
+        if (t == 0) ipiv[row0 + j] = row0 + p;
+        // post the pivot row (the new row j) and, when it moves, row j
+        if (t == pt) {
+#pragma unroll
+            for (int i = 0; i < RPT; ++i)
+                if (i == pi) {
+#pragma unroll
+                    for (int c = 0; c < W; ++c) prow[c] = v[i][c];
+                }
+        }
+        if (t == j && p != j) {
+#pragma unroll
+            for (int c = 0; c < W; ++c) jrow[c] = v[0][c];
+        }
+        __syncthreads();
+        if (p != j) {
+            if (t == j) {
+#pragma unroll
+                for (int c = 0; c < W; ++c) v[0][c] = prow[c];
+            }
+            if (t == pt) {
+#pragma unroll
+                for (int i = 0; i < RPT; ++i)
+                    if (i == pi) {
+#pragma unroll
+                        for (int c = 0; c < W; ++c) v[i][c] = jrow[c];
+                    }
+            }
+        }
+        const float piv = prow[j];
+        if (pivot_mag > 0.0f && piv != 0.0f) {
+            float u[W];
+#pragma unroll
+            for (int c = j + 1; c < W; ++c) u[c] = prow[c];
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                const int r = t + i * LEAF_THREADS;
+                const bool below = r > j && r < m;
+                const float l = v[i][j] / piv;
+                v[i][j] = below ? l : v[i][j];
+#pragma unroll
+                for (int c = j + 1; c < W; ++c) v[i][c] = below ? v[i][c] - l * u[c] : v[i][c];
+            }
+        } else if (t == 0 && *info == 0) {
+            *info = (int)(row0 + j + 1);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < W; ++c) {
+        float *pc = P + (int64_t)c * lda;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+            const uint32_t r = (uint32_t)(t + i * LEAF_THREADS);
+            if (r < (uint32_t)m && c < w) pc[r] = v[i][c];
+        }
+    }
+}
+
+// The same factorization for panels taller than the register-resident
+// kernel takes: the panel stays in memory and every column pass walks it.
+__global__ __launch_bounds__(LEAF_THREADS) void lu_leaf_tall_kernel(float *__restrict__ P,
+                                                                   int64_t lda, int64_t m, int w,
+                                                                   int64_t *__restrict__ ipiv,
+                                                                   int64_t row0,
+                                                                   int *__restrict__ info)
+{
     __shared__ float sbest[LEAF_THREADS];
     __shared__ int64_t sidx[LEAF_THREADS];
-    __shared__ float urow[LEAF];
+    __shared__ float urow[PANEL_LEAF];
     const int t = threadIdx.x;
     for (int j = 0; j < w; ++j) {
         float *col = P + (int64_t)j * lda;
@@ -82,64 +246,128 @@ __global__ __launch_bounds__(LEAF_THREADS) void lu_leaf_kernel(float *__restrict
     }
 }
 
-// Row interchanges k0..k1-1 (ipiv global rows, applied in order) on ncols
-// columns starting at C (row 0 of the matrix); one thread per column.
-__global__ __launch_bounds__(256) void laswp_kernel(float *__restrict__ C, int64_t ldc,
-                                                   int64_t ncols, const int64_t *__restrict__ ipiv,
-                                                   int64_t k0, int64_t k1)
+// Row interchanges k0..k1-1, in order (row k with row ipiv[k]; an entry
+// outside [0, nrows) is skipped), on ncols columns of C (row 0 of the
+// matrix, leading dimension ldc).  Column index c is matrix column c below
+// gap0 and c + gapw from there on, so that a band of gapw columns is left
+// alone.  The interchanges are taken SWAP_BLOCK at a time and each block is
+// composed into one permutation of at most 2 * SWAP_BLOCK rows ("slots":
+// slot i < nb is row k + i, a row outside the block takes slot nb + i for
+// the first i that names it).  Each wavefront composes the permutation with
+// lane s tracking slot s, then moves SWAP_COLS_PER_WAVE columns: S lanes
+// per column (S = the power of two >= 2 nb), lane s loading the row of
+// slot s, receiving the value its slot ends up with from the lane that
+// loaded it, and storing it -- one load and one store per moved element,
+// no chain of dependent swaps.
+template <int S>
+__device__ inline void laswp_move(float *__restrict__ C, int64_t ldc, int64_t ncols, int64_t gap0,
+                                  int64_t gapw, int64_t cbase, int lane, int64_t row, int content)
 {
-    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (c >= ncols) return;
-    float *col = C + c * ldc;
-    for (int64_t k = k0; k < k1; ++k) {
-        const int64_t p = ipiv[k];
-        if (p != k) {
-            const float x = col[k];
-            col[k] = col[p];
-            col[p] = x;
-        }
+    constexpr int CPP = 64 / S;                       // columns per pass
+    constexpr int PASSES = SWAP_COLS_PER_WAVE / CPP;
+    const int s = lane & (S - 1), g = lane / S;
+    const int64_t rs = __shfl(row, s);
+    const int fs = __shfl(content, s);
+    const bool moved = rs >= 0 && fs != s;
+    float val[PASSES];
+    float *colp[PASSES];
+#pragma unroll
+    for (int q = 0; q < PASSES; ++q) {
+        int64_t c = cbase + q * CPP + g;
+        const bool act = moved && c < ncols;
+        if (c >= gap0) c += gapw;
+        colp[q] = act ? C + c * ldc : nullptr;
+        val[q] = act ? colp[q][rs] : 0.0f;
+    }
+#pragma unroll
+    for (int q = 0; q < PASSES; ++q) {
+        const float nv = __shfl(val[q], g * S + fs);
+        if (colp[q]) colp[q][rs] = nv;
     }
 }
 
-// B (n x ncols, n <= LEAF) := T^{-1} B for T the n x n lower unit (UPPER
-// false) or upper (UPPER true) triangle at T; one thread per column of B,
-// T staged in LDS.
-template <bool UPPER>
+__global__ __launch_bounds__(SWAP_THREADS) void laswp_kernel(float *__restrict__ C, int64_t ldc,
+                                                            int64_t nrows, int64_t ncols,
+                                                            int64_t gap0, int64_t gapw,
+                                                            const int64_t *__restrict__ ipiv,
+                                                            int64_t k0, int64_t k1)
+{
+    const int t = threadIdx.x & 63;
+    const int64_t cbase =
+        ((int64_t)blockIdx.x * (SWAP_THREADS / 64) + (threadIdx.x >> 6)) * SWAP_COLS_PER_WAVE;
+    if (cbase >= ncols) return;  // whole wavefront past the last column
+    for (int64_t kb = k0; kb < k1; kb += SWAP_BLOCK) {
+        const int nb = (int)(k1 - kb < SWAP_BLOCK ? k1 - kb : SWAP_BLOCK);
+        int64_t p = -1;
+        if (t < nb) {
+            p = ipiv[kb + t];
+            if (p < 0 || p >= nrows) p = kb + t;
+        }
+        int first = t;
+        for (int i = 0; i < nb; ++i) {
+            const int64_t q = __shfl(p, i);
+            if (i < t && q == p && first == t) first = i;
+        }
+        int pslot = -1;
+        if (t < nb) pslot = (p >= kb && p < kb + nb) ? (int)(p - kb) : nb + first;
+        // row of slot t
+        const int src = t >= nb ? t - nb : 0;
+        const int64_t q = __shfl(p, src);
+        const int qs = __shfl(pslot, src);
+        int64_t row = -1;
+        if (t < nb) row = kb + t;
+        else if (t < 2 * nb && qs == t) row = q;
+        // compose: content = slot whose original value ends in slot t
+        int content = t;
+        for (int i = 0; i < nb; ++i) {
+            const int b = __shfl(pslot, i);
+            const int ca = __shfl(content, i), cb = __shfl(content, b);
+            if (t == i) content = cb;
+            else if (t == b) content = ca;
+        }
+        if (nb <= 8)
+            laswp_move<16>(C, ldc, ncols, gap0, gapw, cbase, t, row, content);
+        else if (nb <= 16)
+            laswp_move<32>(C, ldc, ncols, gap0, gapw, cbase, t, row, content);
+        else
+            laswp_move<64>(C, ldc, ncols, gap0, gapw, cbase, t, row, content);
+    }
+}
+
+// B (n x ncols, n <= N) := T^{-1} B for T the n x n lower unit (UPPER
+// false) or upper (UPPER true) triangle at T.  N lanes per column (lane i
+// holds row i of T and x_i), 64 / N columns per wavefront; x_k reaches the
+// other rows by a lane shuffle once it is final.  The lower solve takes
+// the terms of x_i in the order k = 0, 1, ..., i-1; the upper one in the
+// order k = n-1, ..., i+1, then divides by the diagonal.
+template <bool UPPER, int N>
 __global__ __launch_bounds__(256) void trsm_leaf_kernel(const float *__restrict__ T, int64_t ldt,
                                                        float *__restrict__ B, int64_t ldb, int n,
                                                        int64_t ncols)
 {
-    __shared__ float sT[LEAF * LEAF];
-    for (int e = threadIdx.x; e < n * n; e += 256) sT[e] = T[(e % n) + (int64_t)(e / n) * ldt];
-    __syncthreads();
-    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (c >= ncols) return;
-    float x[LEAF];
-    float *col = B + c * ldb;
+    constexpr int CPW = 64 / N;
+    const int lane = threadIdx.x & 63, i = lane % N, g = lane / N;
+    const int64_t c = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * CPW + g;
+    const bool act = c < ncols && i < n;
+    float trow[N];
 #pragma unroll
-    for (int i = 0; i < LEAF; ++i)
-        if (i < n) x[i] = col[i];
+    for (int k = 0; k < N; ++k) trow[k] = (i < n && k < n) ? T[i + (int64_t)k * ldt] : 0.0f;
+    float x = act ? B[c * ldb + i] : 0.0f;
     if (!UPPER) {
 #pragma unroll
-        for (int i = 0; i < LEAF; ++i)
-#pragma unroll
-            for (int k = 0; k < LEAF; ++k)
-                if (k < i && i < n) x[i] -= sT[i + k * n] * x[k];
+        for (int k = 0; k < N - 1; ++k) {
+            const float xk = __shfl(x, g * N + k);
+            if (i > k) x -= trow[k] * xk;
+        }
     } else {
 #pragma unroll
-        for (int ii = 0; ii < LEAF; ++ii) {
-            const int i = LEAF - 1 - ii;
-            if (i < n) {
-#pragma unroll
-                for (int k = 0; k < LEAF; ++k)
-                    if (k > i && k < n) x[i] -= sT[i + k * n] * x[k];
-                x[i] = x[i] / sT[i + i * n];
-            }
+        for (int k = N - 1; k >= 0; --k) {
+            if (i == k && k < n) x = x / trow[k];
+            const float xk = __shfl(x, g * N + k);
+            if (i < k) x -= trow[k] * xk;
         }
     }
-#pragma unroll
-    for (int i = 0; i < LEAF; ++i)
-        if (i < n) col[i] = x[i];
+    if (act) B[c * ldb + i] = x;
 }
 
 __global__ void zero_info_kernel(int *info) { *info = 0; }
@@ -162,12 +390,39 @@ int gemm(const Lu &c, int64_t m, int64_t n, int64_t k, const float *A, int64_t l
     return misgemm_sgemm('N', 'N', m, n, k, -1.0f, A, lda, B, ldb, 1.0f, C, ldc, c.mode, c.s);
 }
 
-int laswp(const Lu &c, float *C, int64_t ldc, int64_t ncols, int64_t k0, int64_t k1)
+// Interchanges k0..k1-1 on ncols columns of C (all rows of the matrix),
+// skipping the band of gapw columns at gap0.
+int laswp(const Lu &c, float *C, int64_t ldc, int64_t ncols, int64_t gap0, int64_t gapw,
+          int64_t k0, int64_t k1)
 {
     if (ncols <= 0 || k1 <= k0) return 0;
-    hipLaunchKernelGGL(laswp_kernel, dim3((unsigned)((ncols + 255) / 256)), dim3(256), 0, c.s, C,
-                       ldc, ncols, c.ipiv, k0, k1);
+    constexpr int cols_per_block = SWAP_THREADS / 64 * SWAP_COLS_PER_WAVE;
+    hipLaunchKernelGGL(laswp_kernel, dim3((unsigned)((ncols + cols_per_block - 1) / cols_per_block)),
+                       dim3(SWAP_THREADS), 0, c.s, C, ldc, c.n, ncols, gap0, gapw, c.ipiv, k0,
+                       k1);
     return check(hipGetLastError());
+}
+
+template <bool UPPER, int N>
+void launch_trsm_leaf_n(const Lu &c, const float *T, int64_t ldt, float *B, int64_t ldb, int n,
+                        int64_t ncols)
+{
+    constexpr int cols_per_block = 4 * (64 / N);
+    hipLaunchKernelGGL((trsm_leaf_kernel<UPPER, N>),
+                       dim3((unsigned)((ncols + cols_per_block - 1) / cols_per_block)), dim3(256),
+                       0, c.s, T, ldt, B, ldb, n, ncols);
+}
+
+template <bool UPPER>
+void launch_trsm_leaf(const Lu &c, const float *T, int64_t ldt, float *B, int64_t ldb, int n,
+                      int64_t ncols)
+{
+    if (n <= 8)
+        launch_trsm_leaf_n<UPPER, 8>(c, T, ldt, B, ldb, n, ncols);
+    else if (n <= 16)
+        launch_trsm_leaf_n<UPPER, 16>(c, T, ldt, B, ldb, n, ncols);
+    else
+        launch_trsm_leaf_n<UPPER, LEAF>(c, T, ldt, B, ldb, n, ncols);
 }
 
 // B (n x ncols) := T^{-1} B, T lower unit or upper n x n, recursively: the
@@ -177,13 +432,10 @@ int trsm(const Lu &c, bool upper, const float *T, int64_t ldt, float *B, int64_t
 {
     if (n == 0 || ncols == 0) return 0;
     if (n <= LEAF) {
-        const dim3 grid((unsigned)((ncols + 255) / 256));
         if (upper)
-            hipLaunchKernelGGL(trsm_leaf_kernel<true>, grid, dim3(256), 0, c.s, T, ldt, B, ldb,
-                               (int)n, ncols);
+            launch_trsm_leaf<true>(c, T, ldt, B, ldb, (int)n, ncols);
         else
-            hipLaunchKernelGGL(trsm_leaf_kernel<false>, grid, dim3(256), 0, c.s, T, ldt, B, ldb,
-                               (int)n, ncols);
+            launch_trsm_leaf<false>(c, T, ldt, B, ldb, (int)n, ncols);
         return check(hipGetLastError());
     }
     const int64_t h = (n / 2 + LEAF - 1) / LEAF * LEAF;
@@ -198,27 +450,56 @@ int trsm(const Lu &c, bool upper, const float *T, int64_t ldt, float *B, int64_t
     return trsm(c, true, T, ldt, B, ldb, h, ncols);
 }
 
+// Rows per thread of the register-resident leaf for an m-row panel (a
+// power of two), or 0 when the panel is taller than it takes.
+int leaf_rpt(int64_t m)
+{
+    for (int rpt = 1; rpt <= 16; rpt *= 2)
+        if (m <= (int64_t)rpt * LEAF_THREADS) return rpt;
+    return 0;
+}
+
+// Widest leaf panel whose m x w values fit LEAF_REGS registers per thread.
+int64_t leaf_width(int64_t m)
+{
+    const int rpt = leaf_rpt(m);
+    if (rpt == 0) return PANEL_LEAF;
+    return LEAF_REGS / rpt < PANEL_LEAF ? LEAF_REGS / rpt : PANEL_LEAF;
+}
+
+int leaf(const Lu &c, float *P, int64_t m, int w, int64_t j0)
+{
+    const dim3 grid(1), block(LEAF_THREADS);
+    switch (leaf_rpt(m)) {
+    case 1: hipLaunchKernelGGL((lu_leaf_kernel<1, PANEL_LEAF>), grid, block, 0, c.s, P, c.lda, (int)m, w, c.ipiv, j0, c.info); break;
+    case 2: hipLaunchKernelGGL((lu_leaf_kernel<2, PANEL_LEAF>), grid, block, 0, c.s, P, c.lda, (int)m, w, c.ipiv, j0, c.info); break;
+    case 4: hipLaunchKernelGGL((lu_leaf_kernel<4, PANEL_LEAF>), grid, block, 0, c.s, P, c.lda, (int)m, w, c.ipiv, j0, c.info); break;
+    case 8: hipLaunchKernelGGL((lu_leaf_kernel<8, PANEL_LEAF>), grid, block, 0, c.s, P, c.lda, (int)m, w, c.ipiv, j0, c.info); break;
+    case 16: hipLaunchKernelGGL((lu_leaf_kernel<16, LEAF_REGS / 16>), grid, block, 0, c.s, P, c.lda, (int)m, w, c.ipiv, j0, c.info); break;
+    default: hipLaunchKernelGGL(lu_leaf_tall_kernel, grid, block, 0, c.s, P, c.lda, m, w, c.ipiv, j0, c.info); break;
+    }
+    return check(hipGetLastError());
+}
+
 // Factor columns j0 .. j0+w-1 over rows j0 .. n-1.
 int getrf(const Lu &c, int64_t j0, int64_t w)
 {
     const int64_t m = c.n - j0;
     float *P = c.A + j0 + j0 * c.lda;
-    if (w <= LEAF) {
-        hipLaunchKernelGGL(lu_leaf_kernel, dim3(1), dim3(LEAF_THREADS), 0, c.s, P, c.lda, m,
-                           (int)w, c.ipiv, j0, c.info);
-        return check(hipGetLastError());
-    }
-    const int64_t w1 = (w / 2 + LEAF - 1) / LEAF * LEAF, w2 = w - w1;
+    const int64_t lw = leaf_width(m);
     int rc;
+    if (w <= lw) {
+        if ((rc = leaf(c, P, m, (int)w, j0))) return rc;
+        // this leaf's interchanges on every other column
+        return laswp(c, c.A, c.lda, c.n - w, j0, w, j0, j0 + w);
+    }
+    const int64_t w1 = (w / 2 + lw - 1) / lw * lw, w2 = w - w1;
     if ((rc = getrf(c, j0, w1))) return rc;
-    float *right = c.A + (j0 + w1) * c.lda;  // row 0 of the right part
-    if ((rc = laswp(c, right, c.lda, w2, j0, j0 + w1))) return rc;
     if ((rc = trsm(c, false, P, c.lda, P + w1 * c.lda, c.lda, w1, w2))) return rc;
     if ((rc = gemm(c, m - w1, w2, w1, P + w1, c.lda, P + w1 * c.lda, c.lda,
                    P + w1 + w1 * c.lda, c.lda)))
         return rc;
-    if ((rc = getrf(c, j0 + w1, w2))) return rc;
-    return laswp(c, c.A + j0 * c.lda, c.lda, w1, j0 + w1, j0 + w);
+    return getrf(c, j0 + w1, w2);
 }
 
 bool lu_mode_ok(int mode) { return mode == MISGEMM_FP32 || mode == MISGEMM_BF16X3; }
@@ -259,7 +540,7 @@ int misgemm_sgetrs(int64_t n, int64_t nrhs, const float *A, int64_t lda, const i
     if (n == 0 || nrhs == 0) return 0;
     const Lu c{const_cast<float *>(A), lda, n, const_cast<int64_t *>(ipiv), nullptr, mode,
                (hipStream_t)stream};
-    int rc = laswp(c, B, ldb, nrhs, 0, n);
+    int rc = laswp(c, B, ldb, nrhs, nrhs, 0, 0, n);
     if (rc == 0) rc = trsm(c, false, A, lda, B, ldb, n, nrhs);
     if (rc == 0) rc = trsm(c, true, A, lda, B, ldb, n, nrhs);
     return rc;

@@ -60,9 +60,9 @@ def _permuted(a, ipiv):
 def test_lu_unique_pivots_match_oracle(mode):
     """Permuted diagonally dominant matrices: every pivot is unique by a wide
     margin, so the GPU pivots equal the oracle's and the factors agree to
-    FP32 accuracy; sizes around the 32-column leaf and with several levels."""
+    FP32 accuracy; sizes around the leaf widths and with several levels."""
     rng = np.random.default_rng(50)
-    for n in (1, 31, 32, 33, 100, 257):
+    for n in (1, 7, 8, 9, 31, 32, 33, 100, 257):
         d = rng.uniform(-1, 1, (n, n)) + np.diag(rng.uniform(n, 2 * n, n))
         a = d[rng.permutation(n)].astype(np.float32)
         lu, ipiv, info = _factor(a, mode)[:3]
@@ -131,3 +131,51 @@ def test_lu_singular_and_errors():
     mg.sgetrf(0, None, 1, None, info_t, 0)
     torch.cuda.synchronize()
     assert int(info_t.item()) == 0
+
+
+def test_getrs_row_swaps_any_pivots():
+    """Identity factors (L = U = I), so sgetrs only applies the interchanges:
+    row k with row ipiv[k] for k = 0 .. n-1 in order, for pivot lists a
+    factorization never makes (targets above k, repeats, rows inside and
+    outside a block of interchanges, entries outside [0, n) that must be
+    skipped), several right-hand sides and a padded ldb; the result must be
+    exactly the sequential swaps done here."""
+    import torch
+    mg = _mg()
+    rng = np.random.default_rng(54)
+    d = torch.device("cuda:0")
+    for n, nrhs, ldb in ((1, 1, 1), (37, 3, 40), (300, 70, 300), (1000, 1, 1003)):
+        eye = torch.from_numpy(np.eye(n, dtype=np.float32).T.reshape(-1).copy()).to(d)
+        piv = rng.integers(0, n, n)
+        piv[::7] = n - 1                     # one row named many times
+        piv[3::11] = np.arange(3, n, 11) + 1  # the next row (inside a block)
+        piv[5::13] = -1                       # skipped
+        piv[6::17] = n                        # skipped
+        piv = np.clip(piv, -1, n)
+        b = rng.standard_normal((nrhs, ldb)).astype(np.float32)  # column-major, padded
+        B = torch.from_numpy(b.reshape(-1).copy()).to(d)
+        mg.sgetrs(n, nrhs, eye, n, torch.from_numpy(piv.astype(np.int64)).to(d), B, ldb, 0)
+        torch.cuda.synchronize()
+        want = b.copy()
+        for k in range(n):
+            p = int(piv[k])
+            if 0 <= p < n:
+                want[:, [k, p]] = want[:, [p, k]]
+        assert np.array_equal(B.cpu().numpy().reshape(nrhs, ldb), want), n
+
+
+@pytest.mark.parametrize("n", [300, 2100, 9000])
+def test_lu_pivot_ties_take_first_row(n):
+    """Equal largest magnitudes (both signs) in rows held by different
+    threads, register slots and wavefronts of the leaf panel: the pivot is
+    the first of them, as in the oracle; the sizes give one, four and
+    sixteen panel rows per thread."""
+    rng = np.random.default_rng(55)
+    a = rng.uniform(-1, 1, (n, n)).astype(np.float32)
+    rows = sorted({n // 7, n // 3, n // 2 + 1, n - 2, (n // 7) + 1024 if n > 1100 else n - 3})
+    a[rows, 0] = [4.0 if i % 2 else -4.0 for i in range(len(rows))]
+    ipiv = _factor(a, 0)[1]
+    assert ipiv[0] == rows[0], (ipiv[0], rows)
+    lu_o, ipiv_o, _ = oracle.getrf_f64(min(n, 300), a[:300, :300].T.reshape(-1), min(n, 300)) if n == 300 else (None, None, None)
+    if ipiv_o is not None:
+        assert ipiv_o[0] == rows[0]
