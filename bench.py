@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Benchmark of the sgemm hot path on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--workload square|c1|rankk|wide|batch]
+    python bench.py [--steps K] [--warmup W] [--workload square|c1|rankk|wide|skinny|batch|...]
 
 One step is one pass of the workload's GEMMs over seeded synthetic inputs
 that are already resident in HBM.  The default workload is the square sweep
@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="square",
-                    choices=["square", "c1", "rankk", "wide", "batch", "dominant", "peak",
+                    choices=["square", "c1", "rankk", "wide", "skinny", "batch", "dominant", "peak",
                              "dgemm", "host", "lu"],
                     help="dominant: only the 8192^3 NN problem of the square sweep in both "
                          "forms plus a 1 GiB device copy, for counter collection")
@@ -83,6 +83,10 @@ def _workload_problems(workload):
             "rank-k update M=N=16384, K in {128,256,512}, NN, alpha=-1, beta=1, normal(0,1)"
     if workload == "wide":
         return [wl.config4()], "8192^3 NN, alpha=1, beta=0, entries random sign x 2^U[-8,8]"
+    if workload == "skinny":
+        return [wl.config7(*s) for s in wl.SKINNY_SHAPES], \
+            "split-K regime (few output tiles, long K): 512^3, 128x512x8192, " \
+            "512x512x16384, NN, alpha=1.5, beta=-0.5, uniform[-1,1]"
     raise ValueError(workload)
 
 
@@ -314,12 +318,24 @@ def latency(torch, r, mg, mode, calls=1000):
             "back_to_back_us": round(b2b, 3), "calls": calls}
 
 
+def cpu_model():
+    """The host CPU's model name (as lscpu prints it), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline_leg(res, mg, torch, workload):
     """The FP64 oracle timed on a bounded sample of the same inputs, on the
     host's cores; the same sample gives the error of the GPU results."""
     import oracle
     cores = len(os.sched_getaffinity(0))
-    out = {"kind": "oracle", "cores": cores, "unit": "TFLOP/s"}
+    out = {"kind": "oracle", "cores": cores, "unit": "TFLOP/s", "cpu_model": cpu_model()}
     # the full oracle on every problem of the largest size it finishes in
     # about 10-30 s of CPU work (the four 4096^3 problems of the sweep)
     sizes = sorted(set(r.p.m * r.p.n * r.p.k for r in res))
@@ -502,7 +518,8 @@ def batch_line(args, torch, mg):
         "detail": out,
     }
     if "oracle_seconds" in f32:
-        line["cpu_baseline"] = {"value": f32["oracle_flops"] / f32["oracle_seconds"] / 1e12,
+        line["cpu_baseline"] = {"cpu_model": cpu_model(),
+                                "value": f32["oracle_flops"] / f32["oracle_seconds"] / 1e12,
                                 "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
                                 "sample": "32 entries of every one of the 512 problems (one dot "
                                           "product of length K each, with |A||B|); rate = "
@@ -610,7 +627,8 @@ def dgemm_line(args, torch, mg):
                 e["max_over_bound"] = max(e["max_over_bound"], ratio)
                 e["within_bound"] = e["within_bound"] and bool(ok)
         line["error"] = errs
-        line["cpu_baseline"] = {"value": fl_or / t_or / 1e12, "unit": "TFLOP/s", "cores": cores,
+        line["cpu_baseline"] = {"cpu_model": cpu_model(),
+                                "value": fl_or / t_or / 1e12, "unit": "TFLOP/s", "cores": cores,
                                 "kind": "oracle",
                                 "sample": "binary128 oracle on 1024 sampled entries of each "
                                           "problem (one length-K dot product with |A||B| per "
@@ -715,7 +733,8 @@ def lu_line(args, torch, mg):
         t0 = time.perf_counter()
         oracle.getrf_f64(n, np.ascontiguousarray(a.T).reshape(-1), n, nthreads=cores)
         dt = time.perf_counter() - t0
-        line["cpu_baseline"] = {"value": (2.0 / 3.0 * n ** 3) / dt / 1e9, "unit": "GFLOP/s",
+        line["cpu_baseline"] = {"cpu_model": cpu_model(),
+                                "value": (2.0 / 3.0 * n ** 3) / dt / 1e9, "unit": "GFLOP/s",
                                 "cores": cores, "kind": "oracle",
                                 "sample": "FP64 textbook LU of one 2048 x 2048 matrix"}
     return line

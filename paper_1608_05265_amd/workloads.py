@@ -224,6 +224,18 @@ def config5(count: int = 512, seed_case: int = 0, lo: int = 2, hi: int = 64,
             for i, s in enumerate(specs)]
 
 
+SKINNY_SHAPES = [(512, 512, 512), (128, 512, 8192), (512, 512, 16384)]
+
+
+def config7(m: int, n: int, k: int) -> Problem:
+    """Under-filled grids, the split-K regime: few output tiles and a long K
+    (the small square case and skinny outputs of long inner products),
+    alpha=1.5, beta=-0.5, uniform[-1,1], tight ld."""
+    case = SKINNY_SHAPES.index((m, n, k)) if (m, n, k) in SKINNY_SHAPES else 1000 + m
+    return make_problem("N", "N", m, n, k, 1.5, -0.5, seed_for(7, case),
+                        label="skinny%dx%dx%d_NN" % (m, n, k))
+
+
 DGEMM_SIZES = [2048, 4096, 8192]
 
 
