@@ -91,7 +91,7 @@ def test_lu_exact_data_is_exact():
 
 @pytest.mark.parametrize("mode", [0, 1], ids=["fp32", "bf16x3"])
 def test_lu_random_backward_error_and_residual(mode):
-    """Random uniform[-1,1] matrices (the HPL generator's distribution):
+    """Random uniform[-1,1] matrices (uniform entries, as HPL uses):
     valid pivots, |L| <= 1, ||P A - L U|| small against n eps ||L|| ||U||,
     and the solve passes HPL's check (scaled residual < 16 with FP32 eps)."""
     rng = np.random.default_rng(52)
