@@ -63,3 +63,24 @@ def test_integer_inputs_bit_exact(mode):
         cref, _ = oracle.sgemm_f64(ta, tb, p.m, p.n, p.k, 1.0, p.A, p.lda, p.B, p.ldb, 0.0, None,
                                    p.ldc)
         assert np.array_equal(gu.c_dense(p, out).astype(np.float64), cref)
+
+
+def test_random_shapes_default_dispatch():
+    """Seeded random problems through the default dispatch (tuned entries,
+    the size heuristic and automatic split-K for under-filled grids):
+    sizes from 1 to 400 with K log-uniform up to 4096, every transpose pair,
+    alpha and beta including 0, padded leading dimensions, both forms --
+    every entry against the full oracle, C padding untouched."""
+    rng = np.random.default_rng(160805)
+    for case in range(48):
+        m, n = (int(v) for v in rng.integers(1, 401, size=2))
+        k = int(np.exp(rng.uniform(0.0, np.log(4096.0))))
+        ta, tb = wl.TRANS_PAIRS[int(rng.integers(0, 4))]
+        alpha = float(rng.choice([1.0, -0.75, 2.5, 0.0], p=[0.4, 0.25, 0.25, 0.1]))
+        beta = float(rng.choice([0.0, 1.0, 0.5, -2.0]))
+        pad = int(rng.integers(0, 6))
+        p = wl.make_problem(ta, tb, m, n, k, alpha, beta, 9000 + case, pad=pad)
+        for mode in (0, 1):
+            out = gu.run(p, mode)
+            gu.check_full(p, out, "case %d %s%s %dx%dx%d a=%g b=%g pad=%d mode %d"
+                          % (case, ta, tb, m, n, k, alpha, beta, pad, mode))
