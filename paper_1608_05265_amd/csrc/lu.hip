@@ -23,6 +23,7 @@ constexpr int PANEL_LEAF = 8;       // columns of a leaf panel
 constexpr int LEAF_THREADS = 1024;  // threads of the leaf-panel workgroup
 constexpr int LEAF_WAVES = LEAF_THREADS / 64;
 constexpr int LEAF_REGS = 64;       // panel values one thread holds
+constexpr int LEAF_UPD_RPT = 8;     // tallest leaf (rows per thread) that fuses its sibling's update
 constexpr int SWAP_BLOCK = 32;      // interchanges composed into one permutation
 constexpr int SWAP_THREADS = 256;   // laswp workgroup: four wavefronts
 constexpr int SWAP_COLS_PER_WAVE = 16;
@@ -86,9 +87,9 @@ __device__ inline uint64_t wave_max_key(uint64_t k)
 // row0 + j + 1 in *info if no earlier zero pivot did.  ipiv receives
 // global row indices.  Two barriers per column: one after the per-wave
 // maxima are posted, one after the two exchanged rows are posted.
-template <int RPT, int W>
+template <int RPT, int W, bool UPD>
 __global__ __launch_bounds__(LEAF_THREADS) void lu_leaf_kernel(float *__restrict__ P,
-                                                              int64_t lda, int m, int w,
+                                                              int64_t lda, int m, int w, int wl,
                                                               int64_t *__restrict__ ipiv,
                                                               int64_t row0, int *__restrict__ info)
 {
@@ -96,6 +97,7 @@ __global__ __launch_bounds__(LEAF_THREADS) void lu_leaf_kernel(float *__restrict
     static_assert(LEAF_WAVES <= 16, "per-wave maxima are combined in one 16-lane row");
     __shared__ uint64_t wkey[LEAF_WAVES];
     __shared__ float prow[W], jrow[W];
+    __shared__ float su[W][W];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     float v[RPT][W];
 #pragma unroll
@@ -105,6 +107,47 @@ __global__ __launch_bounds__(LEAF_THREADS) void lu_leaf_kernel(float *__restrict
         for (int i = 0; i < RPT; ++i) {
             const uint32_t r = (uint32_t)(t + i * LEAF_THREADS);
             v[i][c] = (r < (uint32_t)m && c < w) ? pc[r] : 0.0f;
+        }
+    }
+    if (UPD && wl > 0) {
+        // The parent node's update from the left sibling leaf (the wl <= W
+        // columns left of the panel, already factored and swapped): U12 = L11^{-1}
+        // A12 on the wl rows above the panel (thread c solves column c, terms
+        // in the order k = 0, 1, ..., as the triangular leaves take them),
+        // then A22 -= A21 U12 on the panel in registers, one column of A21
+        // (one rank-1 term) at a time.
+        if (t < w) {
+            float x[W];
+#pragma unroll
+            for (int q = 0; q < W; ++q)
+                x[q] = q < wl ? P[(int64_t)t * lda + (q - wl)] : 0.0f;
+#pragma unroll
+            for (int q = 1; q < W; ++q)
+                if (q < wl) {
+#pragma unroll
+                    for (int k = 0; k < q; ++k)
+                        x[q] -= P[(int64_t)(k - wl) * lda + (q - wl)] * x[k];
+                }
+#pragma unroll
+            for (int q = 0; q < W; ++q)
+                if (q < wl) {
+                    P[(int64_t)t * lda + (q - wl)] = x[q];
+                    su[q][t] = x[q];
+                }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+            if (q < wl) {  // uniform
+                const float *lq = P + (int64_t)(q - wl) * lda;  // column q of A21
+#pragma unroll
+                for (int i = 0; i < RPT; ++i) {
+                    const uint32_t r = (uint32_t)(t + i * LEAF_THREADS);
+                    const float a = r < (uint32_t)m ? lq[r] : 0.0f;
+#pragma unroll
+                    for (int c = 0; c < W; ++c) v[i][c] -= a * su[q][c];
+                }
+            }
         }
     }
 #pragma unroll
@@ -467,17 +510,30 @@ int64_t leaf_width(int64_t m)
     return LEAF_REGS / rpt < PANEL_LEAF ? LEAF_REGS / rpt : PANEL_LEAF;
 }
 
-int leaf(const Lu &c, float *P, int64_t m, int w, int64_t j0)
+// Factor the leaf panel at P (m x w, top-left element A(j0, j0)); wl > 0
+// (at most the leaf width) first applies the parent node's solve and update
+// from the wl columns left of it (register kernels of up to LEAF_UPD_RPT
+// rows per thread, whose registers leave room for it).
+int leaf(const Lu &c, float *P, int64_t m, int w, int64_t j0, int wl)
 {
     const dim3 grid(1), block(LEAF_THREADS);
-    switch (leaf_rpt(m)) {
-    case 1: hipLaunchKernelGGL((lu_leaf_kernel<1, PANEL_LEAF>), grid, block, 0, c.s, P, c.lda, (int)m, w, c.ipiv, j0, c.info); break;
-    case 2: hipLaunchKernelGGL((lu_leaf_kernel<2, PANEL_LEAF>), grid, block, 0, c.s, P, c.lda, (int)m, w, c.ipiv, j0, c.info); break;
-    case 4: hipLaunchKernelGGL((lu_leaf_kernel<4, PANEL_LEAF>), grid, block, 0, c.s, P, c.lda, (int)m, w, c.ipiv, j0, c.info); break;
-    case 8: hipLaunchKernelGGL((lu_leaf_kernel<8, PANEL_LEAF>), grid, block, 0, c.s, P, c.lda, (int)m, w, c.ipiv, j0, c.info); break;
-    case 16: hipLaunchKernelGGL((lu_leaf_kernel<16, LEAF_REGS / 16>), grid, block, 0, c.s, P, c.lda, (int)m, w, c.ipiv, j0, c.info); break;
-    default: hipLaunchKernelGGL(lu_leaf_tall_kernel, grid, block, 0, c.s, P, c.lda, m, w, c.ipiv, j0, c.info); break;
+#define MISGEMM_LEAF(R, W, U)                                                                   \
+    hipLaunchKernelGGL((lu_leaf_kernel<R, W, U>), grid, block, 0, c.s, P, c.lda, (int)m, w, wl, \
+                       c.ipiv, j0, c.info)
+    const int rpt = leaf_rpt(m);
+    if (wl > 0 && (rpt == 0 || rpt > LEAF_UPD_RPT)) return MISGEMM_E_BAD_CONFIG;
+    switch (rpt) {
+    case 1: if (wl > 0) MISGEMM_LEAF(1, PANEL_LEAF, true); else MISGEMM_LEAF(1, PANEL_LEAF, false); break;
+    case 2: if (wl > 0) MISGEMM_LEAF(2, PANEL_LEAF, true); else MISGEMM_LEAF(2, PANEL_LEAF, false); break;
+    case 4: if (wl > 0) MISGEMM_LEAF(4, PANEL_LEAF, true); else MISGEMM_LEAF(4, PANEL_LEAF, false); break;
+    case 8: if (wl > 0) MISGEMM_LEAF(8, PANEL_LEAF, true); else MISGEMM_LEAF(8, PANEL_LEAF, false); break;
+    case 16: MISGEMM_LEAF(16, LEAF_REGS / 16, false); break;
+    default:
+        hipLaunchKernelGGL(lu_leaf_tall_kernel, grid, block, 0, c.s, P, c.lda, m, w, c.ipiv, j0,
+                           c.info);
+        break;
     }
+#undef MISGEMM_LEAF
     return check(hipGetLastError());
 }
 
@@ -489,11 +545,21 @@ int getrf(const Lu &c, int64_t j0, int64_t w)
     const int64_t lw = leaf_width(m);
     int rc;
     if (w <= lw) {
-        if ((rc = leaf(c, P, m, (int)w, j0))) return rc;
+        if ((rc = leaf(c, P, m, (int)w, j0, 0))) return rc;
         // this leaf's interchanges on every other column
         return laswp(c, c.A, c.lda, c.n - w, j0, w, j0, j0 + w);
     }
-    const int64_t w1 = (w / 2 + lw - 1) / lw * lw, w2 = w - w1;
+    const int64_t w1 = (w / 2 + lw - 1) / lw * lw, w2 = w - w1, m2 = m - w1;
+    const int rpt2 = leaf_rpt(m2);
+    if (w <= 2 * lw && rpt2 > 0 && rpt2 <= LEAF_UPD_RPT && w1 <= leaf_width(m2) &&
+        w2 <= leaf_width(m2)) {
+        // both halves are leaves: the right one applies this node's solve and
+        // update itself (no separate triangular-solve and sgemm launches)
+        if ((rc = leaf(c, P, m, (int)w1, j0, 0))) return rc;
+        if ((rc = laswp(c, c.A, c.lda, c.n - w1, j0, w1, j0, j0 + w1))) return rc;
+        if ((rc = leaf(c, P + w1 + w1 * c.lda, m2, (int)w2, j0 + w1, (int)w1))) return rc;
+        return laswp(c, c.A, c.lda, c.n - w2, j0 + w1, w2, j0 + w1, j0 + w);
+    }
     if ((rc = getrf(c, j0, w1))) return rc;
     if ((rc = trsm(c, false, P, c.lda, P + w1 * c.lda, c.lda, w1, w2))) return rc;
     if ((rc = gemm(c, m - w1, w2, w1, P + w1, c.lda, P + w1 * c.lda, c.lda,
