@@ -198,10 +198,15 @@ def clock_probe(torch, fn, seconds=2.5):
     return clock.summary()
 
 
-PROBE_FLOP = {0: 32 * 32 * 2 * 2, 1: 32 * 32 * 16 * 2}   # per MFMA: 32x32x2 f32, 32x32x16 bf16
+PROBE_FLOP = {0: 32 * 32 * 2 * 2, 1: 32 * 32 * 16 * 2, 2: 16 * 16 * 4 * 2}
+# per MFMA: 32x32x2 f32, 32x32x16 bf16, 16x16x4 f64
 
 
-def measure_peaks(torch, seconds=2.5):
+PROBE_KINDS = {"fp32": (0, "float32", 8000), "bf16": (1, "bfloat16", 16000),
+               "fp64": (2, "float64", 4000)}
+
+
+def measure_peaks(torch, seconds=2.5, kinds=("fp32", "bf16"), datas=("random", "zero")):
     """Sustained matrix-core rate of this GPU (the probe library: four
     independent accumulators per wave, two waves per SIMD, back-to-back
     MFMAs), with random and with zero operands, each after `seconds` of
@@ -218,11 +223,12 @@ def measure_peaks(torch, seconds=2.5):
     gen = torch.Generator().manual_seed(1608)
     stream = torch.cuda.current_stream()
     res = {}
-    for kind, name, iters in ((0, "fp32", 8000), (1, "bf16", 16000)):
-        dt = torch.float32 if kind == 0 else torch.bfloat16
-        for data in ("random", "zero"):
-            ops = ((torch.rand(4096, generator=gen) * 2 - 1).to(dt) if data == "random"
-                   else torch.zeros(4096, dtype=dt)).to(dev)
+    for name in kinds:
+        kind, dtname, iters = PROBE_KINDS[name]
+        dt = getattr(torch, dtname)
+        for data in datas:
+            ops = ((torch.rand(4096, generator=gen, dtype=torch.float64) * 2 - 1).to(dt)
+                   if data == "random" else torch.zeros(4096, dtype=dt)).to(dev)
 
             def launch():
                 rc = lib.probe_mfma_launch(kind, ops.data_ptr(), out.data_ptr(), iters, blocks,
@@ -597,6 +603,12 @@ def dgemm_line(args, torch, mg):
                      "flops_per_launch": 2.0 * pd.m * pd.n * pd.k, "traffic": None},
         "clock": {k: v["clock"] for k, v in out.items()},
     }
+    if not args.no_peak:
+        peak = measure_peaks(torch, kinds=("fp64",), datas=("random",))["fp64_random"]
+        line["roofline"]["measured_peak"] = peak["tflops"]
+        line["roofline"]["frac_of_measured_peak"] = round(f64["dominant_tflops"] /
+                                                          peak["tflops"], 4)
+        line["measured_peak"] = {"fp64_random": peak}
     if not args.no_cpu_baseline:
         import oracle
         cores = len(os.sched_getaffinity(0))

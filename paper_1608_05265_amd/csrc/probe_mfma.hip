@@ -8,9 +8,10 @@
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
 
-// ops: 4096 floats (fp32 probe) or 512 bf16x8 (bf16 probe); out: one float
-// per thread of the grid; iters a multiple of 4.
+// ops: 4096 floats (fp32 probe), 512 bf16x8 (bf16 probe) or 4096 doubles
+// (fp64 probe); out: one float per thread of the grid; iters a multiple of 4.
 __global__ __launch_bounds__(256) void probe_bf16(const bf16x8 *ops, float *out, int iters)
 {
     bf16x8 a[4], b[4];
@@ -53,20 +54,46 @@ __global__ __launch_bounds__(256) void probe_f32(const float *ops, float *out, i
     out[blockIdx.x * 256 + threadIdx.x] = s;
 }
 
+__global__ __launch_bounds__(256) void probe_f64(const double *ops, float *out, int iters)
+{
+    double a[4], b[4];
+    for (int s = 0; s < 4; ++s) {
+        a[s] = ops[(threadIdx.x + 64 * s) % 4096];
+        b[s] = ops[(threadIdx.x * 7 + 131 * s) % 4096];
+    }
+    doublex4 acc[4] = {};
+    for (int i = 0; i < iters; i += 4) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j], b[(j + r) & 3], acc[j], 0, 0, 0);
+    }
+    double s = 0.0;
+    for (int j = 0; j < 4; ++j)
+        for (int e = 0; e < 4; ++e) s += acc[j][e];
+    out[blockIdx.x * 256 + threadIdx.x] = (float)s;
+}
+
 extern "C" {
 
 // kind 0: FP32 MFMA (32x32x2, 4096 flop each), 1: BF16 MFMA (32x32x16,
-// 32768 flop each).  Flops of one launch: blocks * 4 waves * iters * 4 *
-// flop per MFMA.  Returns a hipError_t.
+// 32768 flop each), 2: FP64 MFMA (16x16x4, 2048 flop each).  Flops of one
+// launch: blocks * 4 waves * iters * 4 * flop per MFMA.  Returns a
+// hipError_t.
 int probe_mfma_launch(int kind, const void *ops, float *out, int iters, int blocks, void *stream)
 {
-    if (iters <= 0 || iters % 4 != 0 || blocks <= 0) return (int)hipErrorInvalidValue;
+    if (iters <= 0 || iters % 4 != 0 || blocks <= 0 || kind < 0 || kind > 2)
+        return (int)hipErrorInvalidValue;
     if (kind == 0)
         hipLaunchKernelGGL(probe_f32, dim3(blocks), dim3(256), 0, (hipStream_t)stream,
                            (const float *)ops, out, iters);
-    else
+    else if (kind == 1)
         hipLaunchKernelGGL(probe_bf16, dim3(blocks), dim3(256), 0, (hipStream_t)stream,
                            (const bf16x8 *)ops, out, iters);
+    else
+        hipLaunchKernelGGL(probe_f64, dim3(blocks), dim3(256), 0, (hipStream_t)stream,
+                           (const double *)ops, out, iters);
     return (int)hipGetLastError();
 }
 
