@@ -4,13 +4,16 @@
 // Recursive right-looking LU: factor the left half of the column range,
 // L11^{-1} A12 (recursive triangular solve), A22 -= A21 A12 (one sgemm --
 // the rank-k trailing update), factor A22.  Almost all flops land in sgemm
-// calls of decreasing size.  The leaves are narrow panels (8 columns, 4 or
-// 2 when the panel is taller than 8192 or 16384 rows) that one workgroup
-// factors with the panel held in registers; each leaf's row interchanges
-// are applied to every other column of the matrix right after it, which
-// gives the same result as swapping at each level of the recursion (a
-// column receives the interchanges in pivot order either way, and the
-// columns right of a range are not touched before its left half is done).
+// calls of decreasing size.  The leaves are narrow panels (8 columns, 4
+// when the panel is taller than 8192 rows) that one workgroup factors with
+// the panel held in registers (panels taller than 16384 rows are factored
+// in memory, 8 columns at a time); where both halves of a node are leaves,
+// the right one also applies the node's solve and update.  Each leaf's row
+// interchanges are applied to every other column of the matrix right after
+// it, which gives the same result as swapping at each level of the
+// recursion (a column receives the interchanges in pivot order either way,
+// and the columns right of a range are not touched before its left half is
+// done).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
