@@ -245,9 +245,11 @@ int misgemm_dgemm(char transa, char transb, int64_t m, int64_t n, int64_t k,
  * dividing that column, as LAPACK's getrf does).  Recursive right-looking
  * algorithm: the trailing updates and the off-diagonal parts of the
  * triangular solves are sgemm calls in `mode` (MISGEMM_FP32 or
- * MISGEMM_BF16X3); leaf panels of 8 columns (4 when taller than 8192 rows)
- * are factored by one workgroup, and each leaf's interchanges are applied
- * to the rest of the matrix right after it.
+ * MISGEMM_BF16X3), except the smallest ones, between two sibling leaves,
+ * which the right leaf applies itself in FP32; leaf panels of 8 columns (4
+ * when taller than 8192 rows) are factored by one workgroup, and each
+ * leaf's interchanges are applied to the rest of the matrix right after
+ * it.
  * Asynchronous on `stream`; uses the library scratch of misgemm_sgemm.
  * Errors: -1 n, -2 A, -3 lda, -4 ipiv, -5 info, -6 mode (before any launch).
  */
