@@ -179,3 +179,28 @@ def test_lu_pivot_ties_take_first_row(n):
     lu_o, ipiv_o, _ = oracle.getrf_f64(min(n, 300), a[:300, :300].T.reshape(-1), min(n, 300)) if n == 300 else (None, None, None)
     if ipiv_o is not None:
         assert ipiv_o[0] == rows[0]
+
+
+def test_lu_tall_panels_through_the_solve():
+    """n = 16500: the first panels are taller than the register-resident
+    leaf takes (16384 rows), so the in-memory leaf factors them.  At this
+    size the check is the solve: valid pivots and HPL's scaled residual
+    (matrix-vector products only on the CPU)."""
+    import torch
+    mg = _mg()
+    n = 16500
+    rng = np.random.default_rng(56)
+    a = rng.uniform(-1, 1, (n, n)).astype(np.float32)  # a[i, j], stored column-major below
+    d = torch.device("cuda:0")
+    A = torch.from_numpy(np.ascontiguousarray(a.T).reshape(-1)).to(d)
+    ipiv = torch.zeros(n, dtype=torch.int64, device=d)
+    info = torch.zeros(1, dtype=torch.int32, device=d)
+    mg.sgetrf(n, A, n, ipiv, info, 0)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    piv = ipiv.cpu().numpy()
+    assert np.all(piv >= np.arange(n)) and np.all(piv < n)
+    b = rng.uniform(-1, 1, n).astype(np.float32)
+    x = _solve(A, ipiv, n, b, 0)
+    r = oracle.hpl_scaled_residual(a, x, b, EPS32)
+    assert r < 16.0, r
