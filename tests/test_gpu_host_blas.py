@@ -85,3 +85,34 @@ def test_dgemm_host_against_oracle():
         pad_now = C.reshape(p.n, p.ldc)[:, p.m:].view(np.uint64)
         pad_was = p.C0.reshape(p.n, p.ldc)[:, p.m:].view(np.uint64)
         assert np.array_equal(pad_now, pad_was)
+
+
+def test_fortran_dgemm_symbol_and_sgemm_mode_switch(monkeypatch):
+    """dgemm_ with by-reference arguments against the binary128 oracle; and
+    sgemm_ in the bf16x3 form when MISGEMM_SGEMM_MODE says so (read at each
+    call), within the same bound."""
+    lib = ctypes.CDLL(_mg().library_path())
+    i = lambda v: ctypes.byref(ctypes.c_int(v))
+    d = lambda v: ctypes.byref(ctypes.c_double(v))
+    fp = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    for ta, tb in wl.TRANS_PAIRS:
+        p = wl.make_problem_d(ta, tb, 150, 1100, 77, -0.5, 1.5, 8500, pad=1)
+        C = p.C0.copy()
+        lib.dgemm_(ctypes.c_char_p(ta.encode()), ctypes.c_char_p(tb.encode()), i(p.m), i(p.n),
+                   i(p.k), d(p.alpha), fp(p.A), i(p.lda), fp(p.B), i(p.ldb), d(p.beta), fp(C),
+                   i(p.ldc))
+        cref, den = oracle.dgemm_f128(ta, tb, p.m, p.n, p.k, p.alpha, p.A, p.lda, p.B, p.ldb,
+                                      p.beta, p.C0, p.ldc)
+        ok, mx, _, _ = oracle.check(C.reshape(p.n, p.ldc).T[:p.m, :], cref, den, p.k,
+                                    oracle.tol_d)
+        assert ok, ("dgemm_", ta, tb, mx)
+    p = wl.make_problem("T", "N", 200, 1030, 300, 1.0, -1.0, 8501, pad=2)
+    c32 = p.C0.copy()
+    _fortran_sgemm(p, c32)
+    gu.check_full(p, c32, "sgemm_ fp32")
+    monkeypatch.setenv("MISGEMM_SGEMM_MODE", "bf16x3")
+    cx3 = p.C0.copy()
+    _fortran_sgemm(p, cx3)
+    gu.check_full(p, cx3, "sgemm_ bf16x3")
+    # the two forms round differently on random data: the switch took effect
+    assert not np.array_equal(c32.view(np.uint32), cx3.view(np.uint32))
