@@ -21,7 +21,7 @@
 
 namespace {
 
-constexpr int LEAF = 32;            // rows of a leaf triangular solve
+constexpr int LEAF = 64;            // rows of a leaf triangular solve (one per lane)
 constexpr int PANEL_LEAF = 8;       // columns of a leaf panel
 constexpr int LEAF_THREADS = 1024;  // threads of the leaf-panel workgroup
 constexpr int LEAF_WAVES = LEAF_THREADS / 64;
@@ -467,6 +467,8 @@ void launch_trsm_leaf(const Lu &c, const float *T, int64_t ldt, float *B, int64_
         launch_trsm_leaf_n<UPPER, 8>(c, T, ldt, B, ldb, n, ncols);
     else if (n <= 16)
         launch_trsm_leaf_n<UPPER, 16>(c, T, ldt, B, ldb, n, ncols);
+    else if (n <= 32)
+        launch_trsm_leaf_n<UPPER, 32>(c, T, ldt, B, ldb, n, ncols);
     else
         launch_trsm_leaf_n<UPPER, LEAF>(c, T, ldt, B, ldb, n, ncols);
 }
