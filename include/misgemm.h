@@ -334,7 +334,12 @@ typedef struct misgemm_batch misgemm_batch; /* opaque plan */
  * loaded list, so each XCD's L2 serves few problems), order every list by
  * decreasing work (longest first), and upload the problem and tile tables
  * to device memory owned by the plan.
- * config_id < 0 picks the configuration from the tuning table / heuristics.
+ * config_id < 0 picks the configuration from the tuning table / heuristics;
+ * a tuning-table rule "batch2 <mode> <T> <config> <config2>" instead puts
+ * the problems with m >= T and n >= T on <config> and the others on
+ * <config2>, as two launches that run concurrently (the second on a stream
+ * the plan owns, forked from and joined back to the launching stream with
+ * events, so misgemm_batch_launch stays capturable).
  * On a bad problem returns that problem's argument error (negative, as for
  * misgemm_sgemm) or MISGEMM_E_BATCH and stores its index in *bad_index.
  * Allocates device memory and synchronizes: NOT capturable (returns
@@ -354,7 +359,10 @@ int misgemm_batch_plan(const misgemm_problem *problems, int64_t count, int mode,
 int misgemm_batch_launch(const misgemm_batch *plan, void *stream);
 
 /* Plan facts: tiles, workgroups launched, config id, total flops 2*m*n*k,
- * and the partition of the tiles over the XCDs. */
+ * and the partition of the tiles over the XCDs.  A two-part plan (a tuned
+ * "batch2" rule) reports its larger-problem part in config_id, grid, parts
+ * and part_imbalance, the other part's config and grid in second_*; tiles
+ * and flops cover both. */
 typedef struct {
     int64_t count, tiles, grid;
     int config_id;
@@ -362,6 +370,8 @@ typedef struct {
     double tile_flops;     /* flops of whole tiles, edges padded (>= flops) */
     int parts;             /* tile lists, one per XCD (1 for tiny batches) */
     double part_imbalance; /* largest list's work / mean list work (>= 1) */
+    int second_config_id;  /* -1: one part */
+    int64_t second_grid;
 } misgemm_batch_desc;
 
 int misgemm_batch_info(const misgemm_batch *plan, misgemm_batch_desc *out);

@@ -59,7 +59,8 @@ class BatchDesc(ctypes.Structure):
     _fields_ = [("count", ctypes.c_int64), ("tiles", ctypes.c_int64), ("grid", ctypes.c_int64),
                 ("config_id", ctypes.c_int), ("flops", ctypes.c_double),
                 ("tile_flops", ctypes.c_double), ("parts", ctypes.c_int),
-                ("part_imbalance", ctypes.c_double)]
+                ("part_imbalance", ctypes.c_double), ("second_config_id", ctypes.c_int),
+                ("second_grid", ctypes.c_int64)]
 
 
 def library_path() -> str:
@@ -348,7 +349,8 @@ class Batch:
         _check(_load().misgemm_batch_info(self._h, ctypes.byref(d)), "misgemm_batch_info")
         return {"count": d.count, "tiles": d.tiles, "grid": d.grid, "config_id": d.config_id,
                 "flops": d.flops, "tile_flops": d.tile_flops, "parts": d.parts,
-                "part_imbalance": d.part_imbalance}
+                "part_imbalance": d.part_imbalance, "second_config_id": d.second_config_id,
+                "second_grid": d.second_grid}
 
     def destroy(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value is not None:

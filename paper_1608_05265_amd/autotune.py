@@ -11,7 +11,9 @@ alone leave CUs idle -- then the best one is timed again over a few tile
 orders (group_m); the winner goes into the tuning table that the
 library reads (include/misgemm.h, misgemm_load_tuning).  Batched plans are
 tuned the same way over the configurations with a persistent variant, on
-the batch workload.  The paper fixes its block sizes at compile time; here
+the batch workload, and also as two concurrent parts (problems with m and
+n at or above a threshold on a large-tile configuration, the others on a
+small-tile one) when that is faster.  The paper fixes its block sizes at compile time; here
 the search replaces that choice, per shape.
 """
 from __future__ import annotations
@@ -143,6 +145,51 @@ def tune_batch(problems, reps=5, warmup=2, log=print):
                      "tflops": flops / (timings[best] * 1e-3) / 1e12, "all_ms": timings}
         log("batch mode %d -> %s %.3f ms %.1f TF/s" % (mode, best, timings[best],
                                                        out[mode]["tflops"]))
+        # two-part rules: problems with m, n >= T on a large-tile config,
+        # the rest on a small-tile one, launched concurrently (fork/join on a
+        # second stream, as the library launches a two-part plan)
+        rules = {}
+        side = torch.cuda.Stream()
+        main = torch.cuda.current_stream()
+        bigs = [c for c in mg.configs(mode) if c["bm"] >= 128 and c["bn"] >= 128]
+        smalls = [c for c in mg.configs(mode) if c["bm"] <= 64 and c["bn"] <= 64]
+        for thr in (192, 256, 384):
+            ib = [i for i, p in enumerate(problems) if p.m >= thr and p.n >= thr]
+            isml = [i for i, p in enumerate(problems) if not (p.m >= thr and p.n >= thr)]
+            if not ib or not isml:
+                continue
+            for cb in bigs:
+                for cs in smalls:
+                    try:
+                        pb = mg.Batch([descs[i] for i in ib], mode=mode, config_id=cb["id"])
+                        ps = mg.Batch([descs[i] for i in isml], mode=mode, config_id=cs["id"])
+                    except mg.MisgemmError:
+                        continue
+
+                    def launch(pb=pb, ps=ps):
+                        fork = torch.cuda.Event()
+                        fork.record(main)
+                        side.wait_event(fork)
+                        pb.launch(main)
+                        ps.launch(side)
+                        join = torch.cuda.Event()
+                        join.record(side)
+                        main.wait_event(join)
+                    rules[(thr, cb["name"], cs["name"])] = _time(launch, reps, warmup)
+                    pb.destroy()
+                    ps.destroy()
+        if rules:
+            key = min(rules, key=rules.get)
+            log("batch mode %d: best two-part option m,n >= %d on %s, others on %s: %.3f ms "
+                "(one part: %.3f ms)" % (mode, key[0], key[1], key[2], rules[key],
+                                         timings[best]))
+            if rules[key] < 0.99 * timings[best]:
+                out[mode]["rule"] = {"threshold": key[0], "big": key[1], "small": key[2],
+                                     "ms": rules[key],
+                                     "tflops": flops / (rules[key] * 1e-3) / 1e12}
+                log("batch mode %d -> two parts: m,n >= %d on %s, others on %s: %.3f ms "
+                    "%.1f TF/s" % (mode, key[0], key[1], key[2], rules[key],
+                                   out[mode]["rule"]["tflops"]))
     return out
 
 
@@ -159,6 +206,11 @@ def write_table(path, gemm_rows, batch):
         for mode, b in sorted(batch.items()):
             f.write("batch %d %s\n" % (mode, b["config"]))
             f.write("#   %.1f TFLOP/s on the 512-problem batch\n" % b["tflops"])
+            if "rule" in b:
+                r = b["rule"]
+                f.write("batch2 %d %d %s %s\n" % (mode, r["threshold"], r["big"], r["small"]))
+                f.write("#   %.1f TFLOP/s on the 512-problem batch, two concurrent parts\n"
+                        % r["tflops"])
 
 
 def main(argv=None):

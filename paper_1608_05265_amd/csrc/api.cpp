@@ -81,6 +81,12 @@ struct TuneEntry {
 };
 std::vector<TuneEntry> g_tuning;
 int g_batch_config[2] = {-1, -1};  // per mode, from "batch" lines
+// per mode, from "batch2" lines: problems with m and n >= threshold use
+// config big, the others config small, in two concurrent launches
+struct BatchRule {
+    int threshold, big, small;
+};
+BatchRule g_batch_rule[2] = {{0, -1, -1}, {0, -1, -1}};
 std::mutex g_tune_mutex;
 
 int find_config(const char *name)
@@ -374,7 +380,146 @@ struct misgemm_batch {
     ProbDev *d_probs;
     TileDev *d_tiles;
     int device;
+    // two-part plans: the problems below the size threshold in their own
+    // plan, launched on `side` between the fork and join events
+    misgemm_batch *second;
+    hipStream_t side;
+    hipEvent_t fork, join;
 };
+
+// Build the plan of the problems listed in `index` (already validated) with
+// configuration cfg: tiles, their partition over the XCDs, device tables.
+int build_part(const misgemm_problem *problems, const std::vector<int64_t> &index, int mode,
+               int cfg, const DeviceInfo *dev, misgemm_batch **out, int64_t *bad_index)
+{
+    const auto &table = configs();
+    const misgemm_config_desc &d = table[cfg].desc;
+
+    std::vector<ProbDev> probs;
+    std::vector<TileDev> tiles;
+    std::vector<int64_t> work;   // per-tile K (work of a full tile is bm*bn*k)
+    std::vector<int64_t> first;  // per problem: index of its first tile
+    probs.reserve(index.size());
+    double flops = 0.0, tile_flops = 0.0;
+    for (const int64_t i : index) {
+        const misgemm_problem &p = problems[i];
+        if (p.m == 0 || p.n == 0) continue;
+        if ((p.alpha == 0.0f || p.k == 0) && p.beta == 1.0f) continue;
+        ProbDev pd;
+        const bool ab = p.alpha != 0.0f && p.k > 0;
+        pd.g = make_args(p.m, p.n, ab ? p.k : 0, p.alpha, p.A, p.lda, p.B, p.ldb, p.beta, p.C,
+                         p.ldc);
+        pd.ta = trans_flag(p.transa);
+        pd.tb = trans_flag(p.transb);
+        pd.tiles_m = (p.m + d.bm - 1) / d.bm;
+        pd.tiles_n = (p.n + d.bn - 1) / d.bn;
+        if (pd.tiles_m > INT32_MAX || pd.tiles_n > INT32_MAX || (int64_t)probs.size() >= INT32_MAX) {
+            if (bad_index) *bad_index = i;
+            return MISGEMM_E_TOO_LARGE;
+        }
+        const int32_t idx = (int32_t)probs.size();
+        probs.push_back(pd);
+        first.push_back((int64_t)tiles.size());
+        flops += 2.0 * (double)p.m * (double)p.n * (double)pd.g.k;
+        tile_flops += 2.0 * (double)(pd.tiles_m * d.bm) * (double)(pd.tiles_n * d.bn) *
+                      (double)pd.g.k;
+        for (int64_t tn = 0; tn < pd.tiles_n; ++tn)
+            for (int64_t tm = 0; tm < pd.tiles_m; ++tm) {
+                tiles.push_back({idx, (int32_t)tm, (int32_t)tn, 0});
+                work.push_back(pd.g.k);
+            }
+    }
+    first.push_back((int64_t)tiles.size());
+    const int64_t ntiles = (int64_t)tiles.size();
+    const int occ = table[cfg].batch_occupancy ? table[cfg].batch_occupancy() : 1;
+    int64_t grid = (int64_t)dev->cus * occ;
+    if (grid > ntiles) grid = ntiles;
+    if (grid < 1) grid = 1;
+    const int nx = grid >= MAX_XCD ? MAX_XCD : 1;
+    grid -= grid % nx;
+
+    // Deal the tiles to the XCDs so that each XCD's L2 serves few problems:
+    // problems are cut into chunks of consecutive tiles (tiles of a chunk
+    // share operand panels) of at most 1/(4*nx) of the total work, the
+    // chunks go longest first to the least-loaded XCD, and each XCD orders
+    // its tiles by decreasing K (longest processing time first; stable, so
+    // the tiles of a chunk stay together).
+    int64_t total_work = 0;
+    for (int64_t w : work) total_work += std::max<int64_t>(1, w);
+    const int64_t chunk_cap = std::max<int64_t>(1, (total_work + 4 * nx - 1) / (4 * nx));
+    struct Chunk { int64_t begin, end, work; };
+    std::vector<Chunk> chunks;
+    for (size_t p = 0; p + 1 < first.size(); ++p) {
+        const int64_t b = first[p], e = first[p + 1];
+        if (b == e) continue;
+        const int64_t per = std::max<int64_t>(1, work[(size_t)b]);
+        const int64_t pwork = (e - b) * per;
+        const int64_t pieces = (pwork + chunk_cap - 1) / chunk_cap;
+        const int64_t step = (e - b + pieces - 1) / pieces;
+        for (int64_t c = b; c < e; c += step) {
+            const int64_t ce = std::min(e, c + step);
+            chunks.push_back({c, ce, (ce - c) * per});
+        }
+    }
+    std::stable_sort(chunks.begin(), chunks.end(),
+                     [](const Chunk &a, const Chunk &b) { return a.work > b.work; });
+    std::vector<std::vector<int64_t>> part((size_t)nx);
+    std::vector<int64_t> load((size_t)nx, 0);
+    for (const Chunk &c : chunks) {
+        int best = 0;
+        for (int x = 1; x < nx; ++x)
+            if (load[(size_t)x] < load[(size_t)best]) best = x;
+        load[(size_t)best] += c.work;
+        for (int64_t t = c.begin; t < c.end; ++t) part[(size_t)best].push_back(t);
+    }
+    std::vector<TileDev> sorted;
+    sorted.reserve(tiles.size());
+    BatchSplit split = {};
+    split.nx = nx;
+    int64_t max_load = 0;
+    for (int x = 0; x < nx; ++x) {
+        std::vector<int64_t> &pt = part[(size_t)x];
+        std::stable_sort(pt.begin(), pt.end(),
+                         [&](int64_t a, int64_t b) { return work[(size_t)a] > work[(size_t)b]; });
+        split.off[x] = (int64_t)sorted.size();
+        for (int64_t t : pt) sorted.push_back(tiles[(size_t)t]);
+        max_load = std::max(max_load, load[(size_t)x]);
+    }
+    for (int x = nx; x <= MAX_XCD; ++x) split.off[x] = (int64_t)sorted.size();
+
+    misgemm_batch *b = (misgemm_batch *)calloc(1, sizeof(misgemm_batch));
+    if (!b) return (int)hipErrorOutOfMemory;
+    b->config_id = cfg;
+    b->mode = mode;
+    b->count = (int64_t)index.size();
+    b->ntiles = (int64_t)sorted.size();
+    b->flops = flops;
+    b->tile_flops = tile_flops;
+    b->split = split;
+    b->part_imbalance = total_work > 0 ? (double)max_load * nx / (double)total_work : 1.0;
+    hipGetDevice(&b->device);
+    b->grid = (int)grid;
+    hipError_t e = hipSuccess;
+    if (!probs.empty()) {
+        e = hipMalloc((void **)&b->d_probs, probs.size() * sizeof(ProbDev));
+        if (e == hipSuccess) e = hipMalloc((void **)&b->d_tiles, sorted.size() * sizeof(TileDev));
+        if (e == hipSuccess)
+            e = hipMemcpy(b->d_probs, probs.data(), probs.size() * sizeof(ProbDev),
+                          hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(b->d_tiles, sorted.data(), sorted.size() * sizeof(TileDev),
+                          hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+        if (b->d_probs) hipFree(b->d_probs);
+        if (b->d_tiles) hipFree(b->d_tiles);
+        free(b);
+        return (int)e;
+    }
+    *out = b;
+    return 0;
+}
+
 
 extern "C" {
 
@@ -548,6 +693,7 @@ int misgemm_load_tuning(const char *path)
 {
     std::vector<TuneEntry> entries;
     int batch_cfg[2] = {-1, -1};
+    BatchRule batch_rule[2] = {{0, -1, -1}, {0, -1, -1}};
     if (path != nullptr) {
         FILE *f = fopen(path, "r");
         if (!f) return MISGEMM_E_TUNING_FILE;
@@ -563,6 +709,24 @@ int misgemm_load_tuning(const char *path)
             }
             char name[64];
             int mode;
+            if (strncmp(line, "batch2 ", 7) == 0) {
+                char name2[64];
+                int thr = 0;
+                if (sscanf(line + 7, "%d %d %63s %63s", &mode, &thr, name, name2) != 4 ||
+                    mode < 0 || mode > 1 || thr <= 0) {
+                    rc = MISGEMM_E_TUNING_FILE;
+                    break;
+                }
+                const int b = find_config(name), sm = find_config(name2);
+                if (b < 0 || sm < 0 || configs()[b].desc.mode != mode ||
+                    configs()[sm].desc.mode != mode || !configs()[b].batch ||
+                    !configs()[sm].batch) {
+                    rc = MISGEMM_E_TUNING_FILE;
+                    break;
+                }
+                batch_rule[mode] = {thr, b, sm};
+                continue;
+            }
             if (strncmp(line, "batch ", 6) == 0) {
                 if (sscanf(line + 6, "%d %63s", &mode, name) != 2 || mode < 0 || mode > 1) {
                     rc = MISGEMM_E_TUNING_FILE;
@@ -602,6 +766,8 @@ int misgemm_load_tuning(const char *path)
     g_tuning.swap(entries);
     g_batch_config[0] = batch_cfg[0];
     g_batch_config[1] = batch_cfg[1];
+    g_batch_rule[0] = batch_rule[0];
+    g_batch_rule[1] = batch_rule[1];
     return 0;
 }
 
@@ -647,14 +813,6 @@ int misgemm_batch_plan(const misgemm_problem *problems, int64_t count, int mode,
                     (int64_t)table[i].desc.bm * table[i].desc.bn == smallest) { cfg = (int)i; break; }
         if (cfg < 0) return MISGEMM_E_BAD_CONFIG;
     }
-    const misgemm_config_desc &d = table[cfg].desc;
-
-    std::vector<ProbDev> probs;
-    std::vector<TileDev> tiles;
-    std::vector<int64_t> work;   // per-tile K (work of a full tile is bm*bn*k)
-    std::vector<int64_t> first;  // per problem: index of its first tile
-    probs.reserve((size_t)count);
-    double flops = 0.0, tile_flops = 0.0;
     for (int64_t i = 0; i < count; ++i) {
         const misgemm_problem &p = problems[i];
         rc = validate(p.transa, p.transb, p.m, p.n, p.k, p.alpha, p.A, p.lda, p.B, p.ldb, p.C,
@@ -663,144 +821,84 @@ int misgemm_batch_plan(const misgemm_problem *problems, int64_t count, int mode,
             if (bad_index) *bad_index = i;
             return rc;
         }
-        if (p.m == 0 || p.n == 0) continue;
-        if ((p.alpha == 0.0f || p.k == 0) && p.beta == 1.0f) continue;
-        ProbDev pd;
-        const bool ab = p.alpha != 0.0f && p.k > 0;
-        pd.g = make_args(p.m, p.n, ab ? p.k : 0, p.alpha, p.A, p.lda, p.B, p.ldb, p.beta, p.C,
-                         p.ldc);
-        pd.ta = trans_flag(p.transa);
-        pd.tb = trans_flag(p.transb);
-        pd.tiles_m = (p.m + d.bm - 1) / d.bm;
-        pd.tiles_n = (p.n + d.bn - 1) / d.bn;
-        if (pd.tiles_m > INT32_MAX || pd.tiles_n > INT32_MAX || (int64_t)probs.size() >= INT32_MAX) {
-            if (bad_index) *bad_index = i;
-            return MISGEMM_E_TOO_LARGE;
-        }
-        const int32_t idx = (int32_t)probs.size();
-        probs.push_back(pd);
-        first.push_back((int64_t)tiles.size());
-        flops += 2.0 * (double)p.m * (double)p.n * (double)pd.g.k;
-        tile_flops += 2.0 * (double)(pd.tiles_m * d.bm) * (double)(pd.tiles_n * d.bn) *
-                      (double)pd.g.k;
-        for (int64_t tn = 0; tn < pd.tiles_n; ++tn)
-            for (int64_t tm = 0; tm < pd.tiles_m; ++tm) {
-                tiles.push_back({idx, (int32_t)tm, (int32_t)tn, 0});
-                work.push_back(pd.g.k);
-            }
     }
-    first.push_back((int64_t)tiles.size());
-    const int64_t ntiles = (int64_t)tiles.size();
-    const int occ = table[cfg].batch_occupancy ? table[cfg].batch_occupancy() : 1;
-    int64_t grid = (int64_t)dev->cus * occ;
-    if (grid > ntiles) grid = ntiles;
-    if (grid < 1) grid = 1;
-    const int nx = grid >= MAX_XCD ? MAX_XCD : 1;
-    grid -= grid % nx;
-
-    // Deal the tiles to the XCDs so that each XCD's L2 serves few problems:
-    // problems are cut into chunks of consecutive tiles (tiles of a chunk
-    // share operand panels) of at most 1/(4*nx) of the total work, the
-    // chunks go longest first to the least-loaded XCD, and each XCD orders
-    // its tiles by decreasing K (longest processing time first; stable, so
-    // the tiles of a chunk stay together).
-    int64_t total_work = 0;
-    for (int64_t w : work) total_work += std::max<int64_t>(1, w);
-    const int64_t chunk_cap = std::max<int64_t>(1, (total_work + 4 * nx - 1) / (4 * nx));
-    struct Chunk { int64_t begin, end, work; };
-    std::vector<Chunk> chunks;
-    for (size_t p = 0; p + 1 < first.size(); ++p) {
-        const int64_t b = first[p], e = first[p + 1];
-        if (b == e) continue;
-        const int64_t per = std::max<int64_t>(1, work[(size_t)b]);
-        const int64_t pwork = (e - b) * per;
-        const int64_t pieces = (pwork + chunk_cap - 1) / chunk_cap;
-        const int64_t step = (e - b + pieces - 1) / pieces;
-        for (int64_t c = b; c < e; c += step) {
-            const int64_t ce = std::min(e, c + step);
-            chunks.push_back({c, ce, (ce - c) * per});
-        }
+    // A tuned two-part rule (no explicit config): the problems with m and n
+    // at or above the threshold on one configuration, the rest on another,
+    // launched concurrently; with only one side present, its configuration.
+    BatchRule rule = {0, -1, -1};
+    if (config_id < 0) {
+        std::lock_guard<std::mutex> lock(g_tune_mutex);
+        rule = g_batch_rule[mode];
     }
-    std::stable_sort(chunks.begin(), chunks.end(),
-                     [](const Chunk &a, const Chunk &b) { return a.work > b.work; });
-    std::vector<std::vector<int64_t>> part((size_t)nx);
-    std::vector<int64_t> load((size_t)nx, 0);
-    for (const Chunk &c : chunks) {
-        int best = 0;
-        for (int x = 1; x < nx; ++x)
-            if (load[(size_t)x] < load[(size_t)best]) best = x;
-        load[(size_t)best] += c.work;
-        for (int64_t t = c.begin; t < c.end; ++t) part[(size_t)best].push_back(t);
+    std::vector<int64_t> all, big, small;
+    for (int64_t i = 0; i < count; ++i) {
+        all.push_back(i);
+        if (rule.big >= 0)
+            (problems[i].m >= rule.threshold && problems[i].n >= rule.threshold ? big : small)
+                .push_back(i);
     }
-    std::vector<TileDev> sorted;
-    sorted.reserve(tiles.size());
-    BatchSplit split = {};
-    split.nx = nx;
-    int64_t max_load = 0;
-    for (int x = 0; x < nx; ++x) {
-        std::vector<int64_t> &pt = part[(size_t)x];
-        std::stable_sort(pt.begin(), pt.end(),
-                         [&](int64_t a, int64_t b) { return work[(size_t)a] > work[(size_t)b]; });
-        split.off[x] = (int64_t)sorted.size();
-        for (int64_t t : pt) sorted.push_back(tiles[(size_t)t]);
-        max_load = std::max(max_load, load[(size_t)x]);
+    if (rule.big >= 0 && (big.empty() || small.empty()))
+        return build_part(problems, all, mode, big.empty() ? rule.small : rule.big, dev, plan,
+                          bad_index);
+    if (rule.big < 0) return build_part(problems, all, mode, cfg, dev, plan, bad_index);
+    misgemm_batch *p1 = nullptr, *p2 = nullptr;
+    rc = build_part(problems, big, mode, rule.big, dev, &p1, bad_index);
+    if (rc == 0) rc = build_part(problems, small, mode, rule.small, dev, &p2, bad_index);
+    if (rc == 0) {
+        p1->second = p2;
+        p1->count = count;
+        if (hipStreamCreateWithFlags(&p1->side, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&p1->fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&p1->join, hipEventDisableTiming) != hipSuccess)
+            rc = MISGEMM_E_NO_DEVICE;
     }
-    for (int x = nx; x <= MAX_XCD; ++x) split.off[x] = (int64_t)sorted.size();
-
-    misgemm_batch *b = (misgemm_batch *)calloc(1, sizeof(misgemm_batch));
-    if (!b) return (int)hipErrorOutOfMemory;
-    b->config_id = cfg;
-    b->mode = mode;
-    b->count = count;
-    b->ntiles = (int64_t)sorted.size();
-    b->flops = flops;
-    b->tile_flops = tile_flops;
-    b->split = split;
-    b->part_imbalance = total_work > 0 ? (double)max_load * nx / (double)total_work : 1.0;
-    hipGetDevice(&b->device);
-    b->grid = (int)grid;
-    hipError_t e = hipSuccess;
-    if (!probs.empty()) {
-        e = hipMalloc((void **)&b->d_probs, probs.size() * sizeof(ProbDev));
-        if (e == hipSuccess) e = hipMalloc((void **)&b->d_tiles, sorted.size() * sizeof(TileDev));
-        if (e == hipSuccess)
-            e = hipMemcpy(b->d_probs, probs.data(), probs.size() * sizeof(ProbDev),
-                          hipMemcpyHostToDevice);
-        if (e == hipSuccess)
-            e = hipMemcpy(b->d_tiles, sorted.data(), sorted.size() * sizeof(TileDev),
-                          hipMemcpyHostToDevice);
+    if (rc != 0) {
+        if (p1) misgemm_batch_destroy(p1);
+        else if (p2) misgemm_batch_destroy(p2);
+        return rc;
     }
-    if (e != hipSuccess) {
-        if (b->d_probs) hipFree(b->d_probs);
-        if (b->d_tiles) hipFree(b->d_tiles);
-        free(b);
-        return (int)e;
-    }
-    *plan = b;
+    *plan = p1;
     return 0;
 }
 
 int misgemm_batch_launch(const misgemm_batch *plan, void *stream)
 {
     if (plan == nullptr) return MISGEMM_E_NULL_PLAN;
-    if (plan->ntiles == 0) return 0;
-    const ConfigEntry &c = configs()[plan->config_id];
-    return (int)c.batch(plan->d_probs, plan->d_tiles, plan->split, plan->grid,
-                        (hipStream_t)stream);
+    const hipStream_t s = (hipStream_t)stream;
+    auto run = [](const misgemm_batch *p, hipStream_t st) -> int {
+        if (p->ntiles == 0) return 0;
+        const ConfigEntry &c = configs()[p->config_id];
+        return (int)c.batch(p->d_probs, p->d_tiles, p->split, p->grid, st);
+    };
+    if (plan->second == nullptr) return run(plan, s);
+    // fork the second part onto the plan's side stream and join it back, so
+    // that the launch stays one unit on `stream` (and one graph when captured)
+    hipError_t e = hipEventRecord(plan->fork, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(plan->side, plan->fork, 0);
+    if (e != hipSuccess) return (int)e;
+    int rc = run(plan, s);
+    const int rc2 = run(plan->second, plan->side);
+    if (rc == 0) rc = rc2;
+    e = hipEventRecord(plan->join, plan->side);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, plan->join, 0);
+    return rc != 0 ? rc : (int)e;
 }
 
 int misgemm_batch_info(const misgemm_batch *plan, misgemm_batch_desc *out)
 {
     if (plan == nullptr) return MISGEMM_E_NULL_PLAN;
     if (out == nullptr) return -2;
+    const misgemm_batch *q = plan->second;
     out->count = plan->count;
-    out->tiles = plan->ntiles;
+    out->tiles = plan->ntiles + (q ? q->ntiles : 0);
     out->grid = plan->grid;
     out->config_id = plan->config_id;
-    out->flops = plan->flops;
-    out->tile_flops = plan->tile_flops;
+    out->flops = plan->flops + (q ? q->flops : 0.0);
+    out->tile_flops = plan->tile_flops + (q ? q->tile_flops : 0.0);
     out->parts = plan->split.nx;
     out->part_imbalance = plan->part_imbalance;
+    out->second_config_id = q ? q->config_id : -1;
+    out->second_grid = q ? q->grid : 0;
     return 0;
 }
 
@@ -808,6 +906,10 @@ int misgemm_batch_destroy(misgemm_batch *plan)
 {
     if (plan == nullptr) return MISGEMM_E_NULL_PLAN;
     hipError_t e = hipDeviceSynchronize();
+    if (plan->second) misgemm_batch_destroy(plan->second);
+    if (plan->fork) (void)hipEventDestroy(plan->fork);
+    if (plan->join) (void)hipEventDestroy(plan->join);
+    if (plan->side) (void)hipStreamDestroy(plan->side);
     if (plan->d_probs) hipFree(plan->d_probs);
     if (plan->d_tiles) hipFree(plan->d_tiles);
     free(plan);

@@ -141,6 +141,12 @@ def test_tuning_table_parsing(mg, tmp_path):
     assert mg.select_config("N", "N", 1024, 1024, 1024, 0) == split["id"]
     mg.load_tuning(str(good))
     assert mg.select_config("N", "T", 3000, 5000, 2500, 0) == f32[-1]["id"]   # within 2x
+    rule = tmp_path / "rule.txt"
+    rule.write_text("misgemm-tuning 1\nbatch2 0 256 fp32p_128x128x16_w64x64 "
+                    "fp32_64x64x16_w32x32\nbatch2 1 192 x3p_128x128x16_w64x64 "
+                    "x3_64x64x32_w32x32\n")
+    mg.load_tuning(str(rule))
+    mg.load_tuning(str(good))
     assert mg.select_config("t", "n", 1000, 2000, 300, 1) == x3[-1]["id"]
     bad_cases = ["nonsense\n", "misgemm-tuning 1\n0 N N 1 1 1 no_such_config\n",
                  "misgemm-tuning 1\n1 N N 64 64 64 %s\n" % f32[0]["name"],  # mode mismatch
@@ -148,7 +154,13 @@ def test_tuning_table_parsing(mg, tmp_path):
                  "misgemm-tuning 1\n0 N N 0 64 64 %s\n" % f32[0]["name"],
                  "misgemm-tuning 1\nbatch 0 %s\n" % f32[0]["name"],  # no persistent variant
                  "misgemm-tuning 1\n0 N N 64 64 64 %s 8 2\n" % nosplit["name"],  # no split-K
-                 "misgemm-tuning 1\n0 N N 64 64 64 %s 8 65\n" % split["name"]]
+                 "misgemm-tuning 1\n0 N N 64 64 64 %s 8 65\n" % split["name"],
+                 # two-part batch rules: no persistent variant, bad threshold,
+                 # mode mismatch, missing field
+                 "misgemm-tuning 1\nbatch2 0 256 %s fp32_64x64x16_w32x32\n" % f32[0]["name"],
+                 "misgemm-tuning 1\nbatch2 0 0 fp32p_128x128x16_w64x64 fp32_64x64x16_w32x32\n",
+                 "misgemm-tuning 1\nbatch2 1 256 fp32p_128x128x16_w64x64 fp32_64x64x16_w32x32\n",
+                 "misgemm-tuning 1\nbatch2 0 256 fp32p_128x128x16_w64x64\n"]
     for i, text in enumerate(bad_cases):
         p = tmp_path / ("bad%d.txt" % i)
         p.write_text(text)

@@ -2,7 +2,8 @@
 configuration (and split factors and tile orders) through the C-ABI,
 writes a tuning table, and the library then dispatches by that table --
 the chosen configuration is the one selected, results through it match the
-oracle, and a batch plan picks the tuned batch configuration.  The packaged
+oracle, and a batch plan picks the tuned batch configuration (or the
+tuned two-part rule).  The packaged
 table is restored afterwards."""
 import pytest
 
@@ -36,7 +37,18 @@ def test_autotune_table_drives_dispatch(tmp_path):
         for mode in (0, 1):
             plan = mg.Batch([(p.transa, p.transb, p.m, p.n, p.k, p.alpha, A, p.lda, B, p.ldb,
                               p.beta, C, p.ldc) for p, (A, B, C) in zip(probs, tensors)], mode)
-            assert plan.info()["config_id"] == names[batch[mode]["config"]]
+            info = plan.info()
+            rule = batch[mode].get("rule")
+            if rule is None:
+                assert info["config_id"] == names[batch[mode]["config"]]
+                assert info["second_config_id"] == -1
+            else:
+                big = [p for p in probs if p.m >= rule["threshold"] and p.n >= rule["threshold"]]
+                if big and len(big) < len(probs):
+                    assert info["config_id"] == names[rule["big"]]
+                    assert info["second_config_id"] == names[rule["small"]]
+                else:
+                    assert info["config_id"] == names[rule["big"] if big else rule["small"]]
             plan.destroy()
     finally:
         mg.load_tuning(mg.TUNING_PATH)

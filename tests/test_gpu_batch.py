@@ -144,3 +144,65 @@ def test_batch_plan_errors():
         mg.Batch([good], mode=0, config_id=0)  # 256x256 has no persistent variant
     assert ei.value.status == 1001
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["fp32", "bf16x3"])
+def test_batch_two_part_rule(mode, tmp_path):
+    """A tuning-table rule "batch2 <mode> 256 <large-tile> <small-tile>": the
+    default plan puts the problems with m, n >= 256 on the large-tile
+    configuration and the rest on the small-tile one, launched concurrently
+    (fork/join on the plan's own stream).  Results are checked against the
+    oracle on sampled entries, equal bit for bit two explicit single-config
+    plans of the same split, and every HIP-graph replay of the launch equals
+    the eager result.  The packaged table is restored afterwards."""
+    import torch
+    import paper_1608_05265_amd as mg
+    big_cfg, small_cfg = (("fp32p_128x128x16_w64x64", "fp32_64x64x16_w32x32") if mode == 0
+                          else ("x3p_128x128x16_w64x64", "x3_64x64x32_w32x32"))
+    names = {c["name"]: c["id"] for c in mg.configs()}
+    table = tmp_path / "tuning.txt"
+    table.write_text("misgemm-tuning 1\nbatch %d %s\nbatch2 %d 256 %s %s\n"
+                     % (mode, small_cfg, mode, big_cfg, small_cfg))
+    problems = wl.config5(count=96, seed_case=3)
+    big = [i for i, p in enumerate(problems) if p.m >= 256 and p.n >= 256]
+    assert 0 < len(big) < len(problems)
+    try:
+        mg.load_tuning(str(table))
+        dev, c0, descs = _setup(problems)
+        plan = mg.Batch(descs, mode=mode)
+        info = plan.info()
+        assert info["config_id"] == names[big_cfg] and info["second_config_id"] == names[small_cfg]
+        assert info["count"] == len(problems)
+        plan.launch()
+        torch.cuda.synchronize()
+        _check_all(problems, dev, False, "two-part mode %d" % mode)
+        eager = [C.clone() for (_, _, C) in dev]
+        # the same split as two explicit single-config plans
+        for (_, _, C), c in zip(dev, c0):
+            C.copy_(c)
+        small = [i for i in range(len(problems)) if i not in set(big)]
+        pb = mg.Batch([descs[i] for i in big], mode=mode, config_id=names[big_cfg])
+        ps = mg.Batch([descs[i] for i in small], mode=mode, config_id=names[small_cfg])
+        pb.launch()
+        ps.launch()
+        torch.cuda.synchronize()
+        for idx, ((_, _, C), e) in enumerate(zip(dev, eager)):
+            assert torch.equal(C.view(torch.int32), e.view(torch.int32)), idx
+        pb.destroy()
+        ps.destroy()
+        # captured and replayed
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            plan.launch()
+        for rep in range(3):
+            for (_, _, C), c in zip(dev, c0):
+                C.copy_(c)
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            for idx, ((_, _, C), e) in enumerate(zip(dev, eager)):
+                assert torch.equal(C.view(torch.int32), e.view(torch.int32)), (rep, idx)
+        del g
+        plan.destroy()
+    finally:
+        mg.load_tuning(mg.TUNING_PATH)
