@@ -204,3 +204,26 @@ def test_lu_tall_panels_through_the_solve():
     x = _solve(A, ipiv, n, b, 0)
     r = oracle.hpl_scaled_residual(a, x, b, EPS32)
     assert r < 16.0, r
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["fp32", "bf16x3"])
+def test_lu_solve_many_rhs_padded_ldb(mode):
+    """sgetrs with 7 right-hand sides and ldb = n + 9: every column passes
+    HPL's check, and the padding rows of B are never written."""
+    import torch
+    mg = _mg()
+    rng = np.random.default_rng(57)
+    n, nrhs, ldb = 1500, 7, 1509
+    a = rng.uniform(-1, 1, (n, n)).astype(np.float32)
+    lu, ipiv, info, A, dpiv = _factor(a, mode)
+    assert info == 0
+    b = rng.uniform(-1, 1, (nrhs, ldb)).astype(np.float32)  # column-major B with padding
+    b[:, n:] = np.float32(7.25)
+    B = torch.from_numpy(b.reshape(-1).copy()).to(A.device)
+    mg.sgetrs(n, nrhs, A, n, dpiv, B, ldb, mode)
+    torch.cuda.synchronize()
+    x = B.cpu().numpy().reshape(nrhs, ldb)
+    assert np.all(x[:, n:] == np.float32(7.25))
+    for j in range(nrhs):
+        r = oracle.hpl_scaled_residual(a, x[j, :n], b[j, :n], EPS32)
+        assert r < 16.0, (j, r)
