@@ -196,3 +196,29 @@ def test_workspace_size_and_ws_argument_checks(mg):
                                 0x3000, 1000, 1, 0x4000, w, None) == -8
     assert any(c["packed"] for c in mg.configs(1))
     assert not any(c["packed"] for c in mg.configs(0))
+
+
+def test_header_is_plain_c(tmp_path):
+    """include/misgemm.h is a C header: a C99 translation unit that includes
+    it and names every entry point compiles without warnings (no HIP or
+    C++ types in the signatures)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    names = ["misgemm_sgemm", "misgemm_sgemm_config", "misgemm_sgemm_split", "misgemm_sgemm_ws",
+             "misgemm_workspace_size", "misgemm_release_workspace", "misgemm_num_configs",
+             "misgemm_config_info", "misgemm_select_config", "misgemm_load_tuning",
+             "misgemm_batch_plan", "misgemm_batch_launch", "misgemm_batch_info",
+             "misgemm_batch_destroy", "misgemm_dgemm", "misgemm_sgetrf", "misgemm_sgetrs",
+             "misgemm_sgemm_host", "misgemm_dgemm_host", "sgemm_", "dgemm_",
+             "misgemm_bf16x3_split", "misgemm_status_string", "misgemm_version"]
+    src = tmp_path / "use.c"
+    src.write_text('#include "misgemm.h"\nvoid *entry_points[] = {%s};\n'
+                   % ", ".join("(void *)&%s" % n for n in names))
+    r = subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-Werror", "-fsyntax-only",
+                        "-I" + inc, str(src)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
