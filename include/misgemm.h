@@ -354,7 +354,8 @@ int misgemm_batch_plan(const misgemm_problem *problems, int64_t count, int mode,
  * Run every problem of the plan in one persistent kernel launch on `stream`.
  * Allocates nothing and does not synchronize, so it may be captured into a
  * HIP graph and replayed.  Launches of one plan on several streams at once
- * race on the plan's C buffers only.
+ * race on the plan's C buffers (and, for a two-part plan, on its fork and
+ * join events); launches of different plans do not interact.
  */
 int misgemm_batch_launch(const misgemm_batch *plan, void *stream);
 
