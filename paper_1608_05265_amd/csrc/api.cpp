@@ -497,7 +497,7 @@ int build_part(const misgemm_problem *problems, const std::vector<int64_t> &inde
     b->tile_flops = tile_flops;
     b->split = split;
     b->part_imbalance = total_work > 0 ? (double)max_load * nx / (double)total_work : 1.0;
-    hipGetDevice(&b->device);
+    (void)hipGetDevice(&b->device);
     b->grid = (int)grid;
     hipError_t e = hipSuccess;
     if (!probs.empty()) {
@@ -511,8 +511,8 @@ int build_part(const misgemm_problem *problems, const std::vector<int64_t> &inde
                           hipMemcpyHostToDevice);
     }
     if (e != hipSuccess) {
-        if (b->d_probs) hipFree(b->d_probs);
-        if (b->d_tiles) hipFree(b->d_tiles);
+        if (b->d_probs) (void)hipFree(b->d_probs);
+        if (b->d_tiles) (void)hipFree(b->d_tiles);
         free(b);
         return (int)e;
     }
@@ -910,8 +910,8 @@ int misgemm_batch_destroy(misgemm_batch *plan)
     if (plan->fork) (void)hipEventDestroy(plan->fork);
     if (plan->join) (void)hipEventDestroy(plan->join);
     if (plan->side) (void)hipStreamDestroy(plan->side);
-    if (plan->d_probs) hipFree(plan->d_probs);
-    if (plan->d_tiles) hipFree(plan->d_tiles);
+    if (plan->d_probs) (void)hipFree(plan->d_probs);
+    if (plan->d_tiles) (void)hipFree(plan->d_tiles);
     free(plan);
     return (int)e;
 }
