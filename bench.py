@@ -495,6 +495,8 @@ def batch_line(args, torch, mg):
                      "launch_avg_ms": avg,
                      "launch_tflops": flops / (avg * 1e-3) / 1e12,
                      "config": cfg["name"], "tiles": info["tiles"], "grid": info["grid"],
+                     "second_config": (mg.config_info(info["second_config_id"])["name"]
+                                       if info.get("second_config_id", -1) >= 0 else None),
                      "tile_efficiency": info["flops"] / info["tile_flops"],
                      "clock": info["clock"]}
         if not args.no_cpu_baseline:
@@ -519,12 +521,20 @@ def batch_line(args, torch, mg):
                                "replayed from a HIP graph", "flops_per_step": flops},
         "pct_of_fp32_peak": round(100.0 * f32["tflops"] / PEAK_FP32, 2),
         "bf16x3": {"value": round(out["bf16x3"]["tflops"], 3),
-                   "pct_of_bf16_mfma_peak": round(100.0 * 6 * out["bf16x3"]["tflops"] / PEAK_BF16, 2)},
+                   "pct_of_bf16_mfma_peak": round(100.0 * 6 * out["bf16x3"]["tflops"] / PEAK_BF16, 2),
+                   "traffic": measured_traffic("batch_bf16x3", BATCH_TRAFFIC_FILE)
+                   if out["bf16x3"]["second_config"] is None else None},
         "roofline": {"bound": "mfma", "kernel": "persistent batch kernel (%s)" % f32["config"],
                      "achieved": round(f32["launch_tflops"], 3), "peak": PEAK_FP32,
                      "unit": "TFLOP/s", "frac": round(f32["launch_tflops"] / PEAK_FP32, 4),
                      "avg_launch_ms": round(f32["launch_avg_ms"], 4),
-                     "flops_per_launch": flops, "traffic": None},
+                     "flops_per_launch": flops,
+                     # counters were taken on one-part plans
+                     "traffic": measured_traffic("batch_fp32", BATCH_TRAFFIC_FILE)
+                     if f32["second_config"] is None else None,
+                     "algorithmic_bytes_per_launch": sum(
+                         4.0 * (p.m * p.k + p.k * p.n + p.m * p.n * (1 + (p.beta != 0.0)))
+                         for p in problems)},
         "detail": out,
     }
     if "oracle_seconds" in f32:
@@ -769,6 +779,7 @@ def lu_line(args, torch, mg):
 
 COPY_BYTES = 1 << 30
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sgemm_dominant8192_hbm_counters.txt")
+BATCH_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "batch512_kernel_trace.txt")
 # what decides the sgemm kernels and which of them runs: their sources and
 # the packaged tuning table
 KERNEL_SOURCES = ["gemm_tile.hpp", "packed_x3.hpp", "registry.hpp", "aux_kernels.hip",
@@ -787,12 +798,13 @@ def kernel_sources_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(form: str):
-    """HBM bytes per launch of the dominant kernel from the committed counter
-    summary (FETCH_SIZE and WRITE_SIZE runs, calibrated on a copy kernel),
-    or None when the kernel sources changed since the counters were taken."""
+def measured_traffic(form: str, path: str = ""):
+    """HBM bytes per launch of a kernel from a committed counter summary
+    (FETCH_SIZE and WRITE_SIZE runs, calibrated on a copy kernel; the
+    dominant-kernel summary unless `path` names another), or None when the
+    kernel sources changed since the counters were taken."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path or TRAFFIC_FILE) as f:
             for line in f:
                 parts = line.split()
                 if len(parts) == 4 and parts[0] == "traffic_bytes_per_launch" and \
@@ -973,7 +985,8 @@ def main():
         torch.cuda.empty_cache()
         b = batch_line(args, torch, mg)
         line["batch512"] = {"fp32_tflops": b["value"], "bf16x3_tflops": b["bf16x3"]["value"],
-                            "detail": b["detail"]}
+                            "roofline": b["roofline"],
+                            "bf16x3_traffic": b["bf16x3"]["traffic"], "detail": b["detail"]}
     print(json.dumps(line))
 
 
