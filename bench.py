@@ -784,13 +784,16 @@ BATCH_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "batch512_kernel_trace.txt")
 # the packaged tuning table
 KERNEL_SOURCES = ["gemm_tile.hpp", "packed_x3.hpp", "registry.hpp", "aux_kernels.hip",
                   "sgemm_f32.hip", "sgemm_x3.hip", "sgemm_x3k.hip"]
+# host code that decides what the kernels touch and in which order (tile
+# choice, tile order, the batch plan's tile lists), hashed with the kernels
+SCHEDULE_SOURCES = ["api.cpp"]
 TUNING_TABLE = os.path.join(ROOT, "paper_1608_05265_amd", "tuning_mi355x.txt")
 
 
 def kernel_sources_hash() -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in KERNEL_SOURCES + SCHEDULE_SOURCES:
         with open(os.path.join(ROOT, "paper_1608_05265_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     with open(TUNING_TABLE, "rb") as fh:
@@ -802,7 +805,8 @@ def measured_traffic(form: str, path: str = ""):
     """HBM bytes per launch of a kernel from a committed counter summary
     (FETCH_SIZE and WRITE_SIZE runs, calibrated on a copy kernel; the
     dominant-kernel summary unless `path` names another), or None when the
-    kernel sources changed since the counters were taken."""
+    kernel sources, the host code that schedules their tiles or the tuning
+    table changed since the counters were taken."""
     try:
         with open(path or TRAFFIC_FILE) as f:
             for line in f:

@@ -45,6 +45,8 @@ def test_kernel_hash_covers_every_kernel_source():
     kernels = {f for f in os.listdir(csrc) if f.endswith((".hip", ".hpp")) and
                not f.startswith(("probe_", "dgemm", "lu."))}
     assert kernels == set(bench.KERNEL_SOURCES)
+    # the tile schedule (choice, order, batch tile lists) is hashed too
+    assert "api.cpp" in bench.SCHEDULE_SOURCES
 
 
 def test_stale_traffic_is_not_reported(tmp_path, monkeypatch):
