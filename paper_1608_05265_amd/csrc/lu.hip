@@ -30,6 +30,11 @@ constexpr int LEAF_UPD_RPT = 8;     // tallest leaf (rows per thread) that fuses
 constexpr int SWAP_BLOCK = 32;      // interchanges composed into one permutation
 constexpr int SWAP_THREADS = 256;   // laswp workgroup: four wavefronts
 constexpr int SWAP_COLS_PER_WAVE = 16;
+// One-workgroup triangular solve for a few right-hand sides (the solve
+// after the factorization): up to TRSV_ROWS rows per launch, used when the
+// right-hand sides number at most TRSV_MAX_RHS.
+constexpr int TRSV_ROWS = 1024;
+constexpr int64_t TRSV_MAX_RHS = 16;
 
 // Pivot search key: the magnitude's bits above the complemented row index.
 // Magnitudes are non-negative, so their bit patterns order as the values
@@ -416,6 +421,68 @@ __global__ __launch_bounds__(256) void trsm_leaf_kernel(const float *__restrict_
     if (act) B[c * ldb + i] = x;
 }
 
+// B (n x 1, n <= TRSV_ROWS, column blockIdx.x of B) := T^{-1} B for T the
+// lower unit (UPPER false) or upper (UPPER true) triangle, one workgroup per
+// right-hand side: wave w holds rows 64w .. 64w+63 (lane = row) in a
+// register, and the 64-row blocks are taken in the solve's order (lower:
+// first to last, upper: last to first).  The wave that owns block k
+// finishes its rows by lane shuffles (the terms in the triangular leaves'
+// order) and posts them to LDS; after one barrier every wave whose rows
+// still depend on block k subtracts its contribution, with the entries of T
+// it needs loaded before the barrier.  No row reads another row's value
+// before that row is final, so the sums are those of substitution by
+// blocks.
+template <bool UPPER>
+__global__ __launch_bounds__(TRSV_ROWS) void trsv_block_kernel(const float *__restrict__ T,
+                                                              int64_t ldt, float *__restrict__ B,
+                                                              int64_t ldb, int n)
+{
+    __shared__ float xs[TRSV_ROWS];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = wave * 64 + lane;
+    const bool live = r < n;
+    float *b = B + (int64_t)blockIdx.x * ldb;
+    float x = live ? b[r] : 0.0f;
+    const int nb = (n + 63) / 64;
+    for (int step = 0; step < nb; ++step) {
+        const int k = UPPER ? nb - 1 - step : step;
+        const bool needs = UPPER ? wave <= k : wave >= k;  // rows that depend on block k
+        float tv[64];
+        const float *tc = T + (int64_t)k * 64 * ldt;      // column 64k of T
+#pragma unroll
+        for (int q = 0; q < 64; ++q)
+            tv[q] = (needs && live && k * 64 + q < n) ? tc[(int64_t)q * ldt + r] : 0.0f;
+        if (wave == k) {
+            if (!UPPER) {
+#pragma unroll
+                for (int q = 0; q < 63; ++q) {
+                    const float xq = __shfl(x, q);
+                    if (lane > q) x -= tv[q] * xq;
+                }
+            } else {
+#pragma unroll
+                for (int q = 63; q >= 0; --q) {
+                    if (lane == q && live) x = x / tv[q];
+                    const float xq = __shfl(x, q);
+                    if (lane < q) x -= tv[q] * xq;
+                }
+            }
+            xs[r] = x;
+        }
+        __syncthreads();
+        if (needs && wave != k) {
+            if (!UPPER) {
+#pragma unroll
+                for (int q = 0; q < 64; ++q) x -= tv[q] * xs[k * 64 + q];
+            } else {
+#pragma unroll
+                for (int q = 63; q >= 0; --q) x -= tv[q] * xs[k * 64 + q];
+            }
+        }
+    }
+    if (live) b[r] = x;
+}
+
 __global__ void zero_info_kernel(int *info) { *info = 0; }
 
 struct Lu {
@@ -473,12 +540,28 @@ void launch_trsm_leaf(const Lu &c, const float *T, int64_t ldt, float *B, int64_
         launch_trsm_leaf_n<UPPER, LEAF>(c, T, ldt, B, ldb, n, ncols);
 }
 
+template <bool UPPER>
+void launch_trsv_block(const Lu &c, const float *T, int64_t ldt, float *B, int64_t ldb, int n,
+                       int64_t ncols)
+{
+    hipLaunchKernelGGL((trsv_block_kernel<UPPER>), dim3((unsigned)ncols), dim3(TRSV_ROWS), 0,
+                       c.s, T, ldt, B, ldb, n);
+}
+
 // B (n x ncols) := T^{-1} B, T lower unit or upper n x n, recursively: the
-// off-diagonal block goes through sgemm.
+// off-diagonal block goes through sgemm.  few_rhs (ncols <= TRSV_MAX_RHS)
+// ends the recursion at TRSV_ROWS rows with the one-workgroup solve.
 int trsm(const Lu &c, bool upper, const float *T, int64_t ldt, float *B, int64_t ldb, int64_t n,
-         int64_t ncols)
+         int64_t ncols, bool few_rhs = false)
 {
     if (n == 0 || ncols == 0) return 0;
+    if (few_rhs && n <= TRSV_ROWS && ncols <= TRSV_MAX_RHS) {
+        if (upper)
+            launch_trsv_block<true>(c, T, ldt, B, ldb, (int)n, ncols);
+        else
+            launch_trsv_block<false>(c, T, ldt, B, ldb, (int)n, ncols);
+        return check(hipGetLastError());
+    }
     if (n <= LEAF) {
         if (upper)
             launch_trsm_leaf<true>(c, T, ldt, B, ldb, (int)n, ncols);
@@ -489,13 +572,13 @@ int trsm(const Lu &c, bool upper, const float *T, int64_t ldt, float *B, int64_t
     const int64_t h = (n / 2 + LEAF - 1) / LEAF * LEAF;
     int rc;
     if (!upper) {
-        if ((rc = trsm(c, false, T, ldt, B, ldb, h, ncols))) return rc;
+        if ((rc = trsm(c, false, T, ldt, B, ldb, h, ncols, few_rhs))) return rc;
         if ((rc = gemm(c, n - h, ncols, h, T + h, ldt, B, ldb, B + h, ldb))) return rc;
-        return trsm(c, false, T + h + h * ldt, ldt, B + h, ldb, n - h, ncols);
+        return trsm(c, false, T + h + h * ldt, ldt, B + h, ldb, n - h, ncols, few_rhs);
     }
-    if ((rc = trsm(c, true, T + h + h * ldt, ldt, B + h, ldb, n - h, ncols))) return rc;
+    if ((rc = trsm(c, true, T + h + h * ldt, ldt, B + h, ldb, n - h, ncols, few_rhs))) return rc;
     if ((rc = gemm(c, h, ncols, n - h, T + h * ldt, ldt, B + h, ldb, B, ldb))) return rc;
-    return trsm(c, true, T, ldt, B, ldb, h, ncols);
+    return trsm(c, true, T, ldt, B, ldb, h, ncols, few_rhs);
 }
 
 // Rows per thread of the register-resident leaf for an m-row panel (a
@@ -612,8 +695,9 @@ int misgemm_sgetrs(int64_t n, int64_t nrhs, const float *A, int64_t lda, const i
     const Lu c{const_cast<float *>(A), lda, n, const_cast<int64_t *>(ipiv), nullptr, mode,
                (hipStream_t)stream};
     int rc = laswp(c, B, ldb, nrhs, nrhs, 0, 0, n);
-    if (rc == 0) rc = trsm(c, false, A, lda, B, ldb, n, nrhs);
-    if (rc == 0) rc = trsm(c, true, A, lda, B, ldb, n, nrhs);
+    const bool few = nrhs <= TRSV_MAX_RHS;
+    if (rc == 0) rc = trsm(c, false, A, lda, B, ldb, n, nrhs, few);
+    if (rc == 0) rc = trsm(c, true, A, lda, B, ldb, n, nrhs, few);
     return rc;
 }
 
