@@ -37,6 +37,9 @@ constexpr int SWAP_COLS_PER_WAVE = 16;
 // right-hand sides number at most TRSV_MAX_RHS.
 constexpr int TRSV_ROWS = 1024;
 constexpr int64_t TRSV_MAX_RHS = 16;
+// Rows of a column whose interchanges are applied in LDS (the column and
+// the pivot list: 8 bytes per row).
+constexpr int LASWP_LDS_ROWS = 16384;
 
 // Pivot search key: the magnitude's bits above the complemented row index.
 // Magnitudes are non-negative, so their bit patterns order as the values
@@ -387,6 +390,39 @@ __global__ __launch_bounds__(SWAP_THREADS) void laswp_kernel(float *__restrict__
     }
 }
 
+// The interchanges k0 .. k1-1 on column blockIdx.x of C (nrows <=
+// LASWP_LDS_ROWS rows, k1 - k0 <= nrows), for the solve's few right-hand
+// sides: the column and the pivot list are staged in LDS, one lane applies
+// the interchanges one by one in order (each an LDS round trip, with the
+// pivot reads independent of the column), and the column is written back.
+// Entries outside [0, nrows) are skipped.
+__global__ __launch_bounds__(SWAP_THREADS) void laswp_lds_kernel(float *__restrict__ C,
+                                                                int64_t ldc, int nrows,
+                                                                const int64_t *__restrict__ ipiv,
+                                                                int64_t k0, int64_t k1)
+{
+    __shared__ float col[LASWP_LDS_ROWS];
+    __shared__ int piv[LASWP_LDS_ROWS];
+    float *c = C + (int64_t)blockIdx.x * ldc;
+    for (int i = threadIdx.x; i < nrows; i += SWAP_THREADS) col[i] = c[i];
+    for (int64_t k = k0 + threadIdx.x; k < k1; k += SWAP_THREADS) {
+        const int64_t p = ipiv[k];
+        piv[k - k0] = (int)((p < 0 || p >= nrows) ? k : p);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int n = (int)(k1 - k0), base = (int)k0;
+        for (int i = 0; i < n; ++i) {
+            const int r = base + i, p = piv[i];
+            const float a = col[r], b = col[p];
+            col[r] = b;
+            col[p] = a;
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nrows; i += SWAP_THREADS) c[i] = col[i];
+}
+
 // B (n x ncols, n <= N) := T^{-1} B for T the n x n lower unit (UPPER
 // false) or upper (UPPER true) triangle at T.  N lanes per column (lane i
 // holds row i of T and x_i), 64 / N columns per wavefront; x_k reaches the
@@ -696,8 +732,15 @@ int misgemm_sgetrs(int64_t n, int64_t nrhs, const float *A, int64_t lda, const i
     if (n == 0 || nrhs == 0) return 0;
     const Lu c{const_cast<float *>(A), lda, n, const_cast<int64_t *>(ipiv), nullptr, mode,
                (hipStream_t)stream};
-    int rc = laswp(c, B, ldb, nrhs, nrhs, 0, 0, n);
     const bool few = nrhs <= TRSV_MAX_RHS;
+    int rc = 0;
+    if (few && n <= LASWP_LDS_ROWS) {
+        hipLaunchKernelGGL(laswp_lds_kernel, dim3((unsigned)nrhs), dim3(SWAP_THREADS), 0, c.s, B,
+                           ldb, (int)n, ipiv, (int64_t)0, n);
+        rc = check(hipGetLastError());
+    } else {
+        rc = laswp(c, B, ldb, nrhs, nrhs, 0, 0, n);
+    }
     if (rc == 0) rc = trsm(c, false, A, lda, B, ldb, n, nrhs, few);
     if (rc == 0) rc = trsm(c, true, A, lda, B, ldb, n, nrhs, few);
     return rc;
