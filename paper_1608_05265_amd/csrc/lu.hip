@@ -14,8 +14,9 @@
 // recursion (a column receives the interchanges in pivot order either way,
 // and the columns right of a range are not touched before its left half is
 // done).  The solve applies the interchanges to the right-hand sides and
-// then the two triangular solves; with few right-hand sides their
-// recursion stops at 1024-row diagonal blocks that one workgroup solves.
+// then the two triangular solves; with few right-hand sides the
+// interchanges run in LDS and the triangular recursion stops at 1024-row
+// diagonal blocks that one workgroup solves.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
