@@ -460,13 +460,21 @@ __global__ __launch_bounds__(256) void trsm_leaf_kernel(const float *__restrict_
     if (act) B[c * ldb + i] = x;
 }
 
+// x of lane q (a constant after unrolling) in every lane, through a scalar
+// register.
+__device__ inline float lane_value(float x, int q)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), q));
+}
+
 // B (n x 1, n <= TRSV_ROWS, column blockIdx.x of B) := T^{-1} B for T the
 // lower unit (UPPER false) or upper (UPPER true) triangle, one workgroup per
 // right-hand side: wave w holds rows 64w .. 64w+63 (lane = row) in a
 // register, and the 64-row blocks are taken in the solve's order (lower:
 // first to last, upper: last to first).  The wave that owns block k
-// finishes its rows by lane shuffles (the terms in the triangular leaves'
-// order) and posts them to LDS; after one barrier every wave whose rows
+// finishes its rows, each final value broadcast from its lane through a
+// scalar register (the terms in the triangular leaves' order), and posts
+// them to LDS; after one barrier every wave whose rows
 // still depend on block k subtracts its contribution, with the entries of T
 // it needs loaded before the barrier.  No row reads another row's value
 // before that row is final, so the sums are those of substitution by
@@ -495,14 +503,14 @@ __global__ __launch_bounds__(TRSV_ROWS) void trsv_block_kernel(const float *__re
             if (!UPPER) {
 #pragma unroll
                 for (int q = 0; q < 63; ++q) {
-                    const float xq = __shfl(x, q);
+                    const float xq = lane_value(x, q);
                     if (lane > q) x -= tv[q] * xq;
                 }
             } else {
 #pragma unroll
                 for (int q = 63; q >= 0; --q) {
                     if (lane == q && live) x = x / tv[q];
-                    const float xq = __shfl(x, q);
+                    const float xq = lane_value(x, q);
                     if (lane < q) x -= tv[q] * xq;
                 }
             }
