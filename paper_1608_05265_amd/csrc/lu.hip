@@ -424,10 +424,18 @@ __global__ __launch_bounds__(SWAP_THREADS) void laswp_lds_kernel(float *__restri
     for (int i = threadIdx.x; i < nrows; i += SWAP_THREADS) c[i] = col[i];
 }
 
+// x of lane q (a constant after unrolling) in every lane, through a scalar
+// register.
+__device__ inline float lane_value(float x, int q)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), q));
+}
+
 // B (n x ncols, n <= N) := T^{-1} B for T the n x n lower unit (UPPER
 // false) or upper (UPPER true) triangle at T.  N lanes per column (lane i
 // holds row i of T and x_i), 64 / N columns per wavefront; x_k reaches the
-// other rows by a lane shuffle once it is final.  The lower solve takes
+// other rows once it is final, by a lane shuffle (a scalar broadcast when
+// the wavefront holds one column).  The lower solve takes
 // the terms of x_i in the order k = 0, 1, ..., i-1; the upper one in the
 // order k = n-1, ..., i+1, then divides by the diagonal.
 template <bool UPPER, int N>
@@ -446,25 +454,18 @@ __global__ __launch_bounds__(256) void trsm_leaf_kernel(const float *__restrict_
     if (!UPPER) {
 #pragma unroll
         for (int k = 0; k < N - 1; ++k) {
-            const float xk = __shfl(x, g * N + k);
+            const float xk = N == 64 ? lane_value(x, k) : __shfl(x, g * N + k);
             if (i > k) x -= trow[k] * xk;
         }
     } else {
 #pragma unroll
         for (int k = N - 1; k >= 0; --k) {
             if (i == k && k < n) x = x / trow[k];
-            const float xk = __shfl(x, g * N + k);
+            const float xk = N == 64 ? lane_value(x, k) : __shfl(x, g * N + k);
             if (i < k) x -= trow[k] * xk;
         }
     }
     if (act) B[c * ldb + i] = x;
-}
-
-// x of lane q (a constant after unrolling) in every lane, through a scalar
-// register.
-__device__ inline float lane_value(float x, int q)
-{
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), q));
 }
 
 // B (n x 1, n <= TRSV_ROWS, column blockIdx.x of B) := T^{-1} B for T the
