@@ -35,6 +35,9 @@ PEAK_FP32 = 157.3      # TFLOP/s, MI355X dense FP32 matrix (= FP32 vector)
 PEAK_BF16 = 2516.6     # TFLOP/s, MI355X dense BF16 matrix
 PEAK_HBM = 8000.0      # GB/s
 PEAK_FP64 = 78.6       # TFLOP/s, MI355X dense FP64 matrix
+# equal measured error: the split form's max and mean normalized error at
+# most this factor above the native form's on the same inputs
+EQUAL_ERROR_RATIO = 1.5
 
 
 def parse():
@@ -51,6 +54,9 @@ def parse():
                     help="skip the oracle leg (used under the profiler)")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched-form measurement in the default run")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the wide-range, rank-k, copy-bandwidth and 256^3 objects of the "
+                         "default run")
     ap.add_argument("--no-peak", action="store_true",
                     help="skip the matrix-core rate probe in the default run")
     ap.add_argument("--problem", default="",
@@ -704,7 +710,7 @@ def host_line(args, torch, mg):
 
 
 def hpl_residual(a, x, b, eps):
-    """HPL's check of a solve (the formula of the paper's Table VI):
+    """HPL's check of a solve (the formula of the paper's Table VII footnote):
     ||A x - b||_inf / (eps (||A||_inf ||x||_inf + ||b||_inf) N), in FP64."""
     a64 = np.asarray(a, dtype=np.float64)
     x64 = np.asarray(x, dtype=np.float64).reshape(-1)
@@ -719,7 +725,7 @@ def lu_line(args, torch, mg):
     pivoting of an N x N uniform[-1,1] matrix and the solve of A x = b, at
     the paper's N = 4608 and at N = 16384, trailing updates in both sgemm
     forms; GFLOP/s by the HPL count (2/3 N^3 + 3/2 N^2) / t, and the scaled
-    residual of Table VI (with FP32's eps, and with the 2^-53 the paper's
+    residual of Table VII's footnote (with FP32's eps, and with the 2^-53 the paper's
     double-precision HPL used)."""
     dev = torch.device("cuda:0")
     rows = []
@@ -761,7 +767,7 @@ def lu_line(args, torch, mg):
     line = {"workload": "LU with partial pivoting + solve (HPL-style), uniform[-1,1]",
             "rows": rows,
             "paper": "Parallella, N=4608, NB=768: 0.495 GFLOP/s, scaled residual 2.11e10 "
-                     "(eps 2^-53), Table VI"}
+                     "(eps 2^-53), Table VII"}
     if not args.no_cpu_baseline:
         import oracle
         cores = len(os.sched_getaffinity(0))
@@ -836,6 +842,158 @@ def dominant_only(args, torch, mg):
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"workload": "dominant", "steps": args.steps, "copy_bytes": COPY_BYTES}))
+
+
+def event_median_ms(torch, fn, reps):
+    """Median and minimum of `reps` calls of fn, each bracketed by HIP events
+    on torch's current stream (the stream the library launches on)."""
+    stream = torch.cuda.current_stream()
+    evs = []
+    for _ in range(reps):
+        s_ = torch.cuda.Event(enable_timing=True)
+        e_ = torch.cuda.Event(enable_timing=True)
+        s_.record(stream)
+        fn()
+        e_.record(stream)
+        evs.append((s_, e_))
+    torch.cuda.synchronize()
+    d = sorted(a.elapsed_time(b) for a, b in evs)
+    return d[len(d) // 2], d[0]
+
+
+def copy_bandwidth(torch, nbytes=COPY_BYTES, reps=20):
+    """Achievable HBM bandwidth on this GPU: a device-to-device copy of
+    `nbytes` (4x the 256 MB Infinity Cache), read + write bytes over the
+    median event-timed copy."""
+    src = torch.empty(nbytes // 4, device="cuda:0")
+    src.fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    med, best = event_median_ms(torch, lambda: dst.copy_(src), reps)
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"gbs": round(2.0 * nbytes / (med * 1e-3) / 1e9, 1),
+            "gbs_best": round(2.0 * nbytes / (best * 1e-3) / 1e9, 1),
+            "bytes_per_copy": 2 * nbytes, "spec_gbs": PEAK_HBM,
+            "how": "device-to-device copy of 1 GiB (read + write), median of %d event-timed "
+                   "copies" % reps}
+
+
+def sampled_error(mg, torch, r, mode, count, seed, cores):
+    """Run r once in `mode` from a pristine C0 and compare `count` random
+    entries with the FP64 oracle: (max, mean normalized error, max/bound,
+    within bound)."""
+    import oracle
+    q = r.p
+    rng = np.random.default_rng(seed)
+    rows = rng.integers(0, q.m, count)
+    cols = rng.integers(0, q.n, count)
+    cref, den = oracle.sgemm_f64_entries(q.transa, q.transb, q.m, q.n, q.k, q.alpha, q.A, q.lda,
+                                         q.B, q.ldb, q.beta, q.C0, q.ldc, rows, cols,
+                                         nthreads=cores)
+    r.reset()
+    r.call(mg, mode)
+    torch.cuda.synchronize()
+    got = r.C.cpu().numpy()[rows + cols * q.ldc]
+    ok, mx, mean, ratio = oracle.check(got, cref, den, q.k)
+    return float(mx), float(mean), float(ratio), bool(ok)
+
+
+def wide_object(args, torch, mg, cores):
+    """The precision form's workload: 8192^3 NN, entries random sign x 2^U[-8,8],
+    alpha = 1, beta = 0, both forms on the same inputs: rate, share of each
+    form's matrix-core peak, and the normalized error of 2048 entries checked
+    against the FP64 oracle, with the split form's error over the native one
+    (equal error: both ratios at most EQUAL_ERROR_RATIO)."""
+    from paper_1608_05265_amd import workloads as wl
+    r = Resident(wl.config4(), torch.device("cuda:0"))
+    p = r.p
+    flops = 2.0 * p.m * p.n * p.k
+    out = {"workload": "8192^3 NN, alpha=1, beta=0, entries random sign x 2^U[-8,8] "
+                       "(continuous U), both forms on the same inputs"}
+    for mode, name in ((mg.FP32, "fp32"), (mg.BF16X3, "bf16x3")):
+        for _ in range(3):
+            r.call(mg, mode)
+        med, best = event_median_ms(torch, lambda: r.call(mg, mode), max(args.steps, 10))
+        tf = flops / (med * 1e-3) / 1e12
+        o = {"tflops": round(tf, 3), "ms": round(med, 4), "ms_min": round(best, 4)}
+        if name == "fp32":
+            o["pct_of_fp32_mfma_peak"] = round(100.0 * tf / PEAK_FP32, 2)
+        else:
+            o["pct_of_bf16_mfma_peak"] = round(100.0 * 6 * tf / PEAK_BF16, 2)
+        if not args.no_cpu_baseline:
+            mx, mean, ratio, ok = sampled_error(mg, torch, r, mode, 2048, 44, cores)
+            o["error"] = {"max_norm_err": mx, "mean_norm_err": mean, "max_over_bound": ratio,
+                          "within_bound": ok, "entries": 2048}
+        out[name] = o
+    if not args.no_cpu_baseline:
+        e0, e1 = out["fp32"]["error"], out["bf16x3"]["error"]
+        rmax = e1["max_norm_err"] / e0["max_norm_err"]
+        rmean = e1["mean_norm_err"] / e0["mean_norm_err"]
+        out["bf16x3_over_fp32_error"] = {"max": round(rmax, 4), "mean": round(rmean, 4)}
+        out["equal_error"] = bool(rmax <= EQUAL_ERROR_RATIO and rmean <= EQUAL_ERROR_RATIO)
+        out["equal_error_rule"] = "split-form max and mean normalized error each at most %.1f x " \
+                                  "the native form's on the same 2048 entries" % EQUAL_ERROR_RATIO
+    del r
+    torch.cuda.empty_cache()
+    return out
+
+
+def rankk_object(args, torch, mg, copy_gbs, cores):
+    """The Linpack-style trailing update, 16384^2 x K for K in {128, 256, 512},
+    alpha = -1, beta = 1, normal(0,1), both forms: rate, algorithmic HBM
+    GB/s, and the time against the larger of its two floors (matrix cores
+    at spec peak, algorithmic bytes at the measured copy bandwidth)."""
+    from paper_1608_05265_amd import workloads as wl
+    rows = []
+    for k in wl.RANKK_KS:
+        r = Resident(wl.config3(k), torch.device("cuda:0"))
+        p = r.p
+        flops = 2.0 * p.m * p.n * p.k
+        nbytes = float(p.bytes())
+        row = {"k": k, "algorithmic_bytes": nbytes, "flops": flops}
+        for mode, name, peak, mult in ((mg.FP32, "fp32", PEAK_FP32, 1),
+                                       (mg.BF16X3, "bf16x3", PEAK_BF16, 6)):
+            for _ in range(3):
+                r.call(mg, mode)
+            med, _ = event_median_ms(torch, lambda: r.call(mg, mode), max(args.steps, 10))
+            mfma_floor = mult * flops / (peak * 1e12) * 1e3
+            hbm_floor = nbytes / (copy_gbs * 1e9) * 1e3
+            o = {"tflops": round(flops / (med * 1e-3) / 1e12, 3), "ms": round(med, 4),
+                 "gbs": round(nbytes / (med * 1e-3) / 1e9, 1),
+                 "mfma_floor_ms": round(mfma_floor, 4), "hbm_floor_ms": round(hbm_floor, 4),
+                 "bound": "mfma" if mfma_floor >= hbm_floor else "hbm",
+                 "frac_of_floor": round(max(mfma_floor, hbm_floor) / med, 4)}
+            if not args.no_cpu_baseline:
+                mx, mean, ratio, ok = sampled_error(mg, torch, r, mode, 512, 45 + k, cores)
+                o["error"] = {"max_over_bound": ratio, "within_bound": ok, "entries": 512}
+            row[name] = o
+        rows.append(row)
+        del r
+        torch.cuda.empty_cache()
+    return {"workload": "16384^2 x K, K in {128,256,512}, NN, alpha=-1, beta=1, normal(0,1) "
+                        "(Linpack-style trailing update)",
+            "hbm_roof_gbs": copy_gbs, "hbm_roof": "measured copy bandwidth", "rows": rows}
+
+
+def c1_object(args, torch, mg):
+    """The 256^3 single call (NN, alpha = 1, beta = 0): per-call latency in
+    both forms (1000 event-timed calls: median and minimum; 1000 calls back
+    to back: host wall time per call) and the rate at the median."""
+    from paper_1608_05265_amd import workloads as wl
+    r = Resident(wl.config1(), torch.device("cuda:0"))
+    flops = 2.0 * r.p.m * r.p.n * r.p.k
+    out = {"workload": "256^3 NN, alpha=1, beta=0, uniform[-1,1]"}
+    for mode, name in ((mg.FP32, "fp32"), (mg.BF16X3, "bf16x3")):
+        for _ in range(20):
+            r.call(mg, mode)
+        lat = latency(torch, r, mg, mode)
+        lat["tflops_at_median"] = round(flops / (lat["median_us"] * 1e-6) / 1e12, 3)
+        lat["config"] = mg.config_info(mg.select_config("N", "N", 256, 256, 256, mode))["name"]
+        out[name] = lat
+    del r
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -933,7 +1091,6 @@ def main():
         "bf16x3": {"value": round(x3["tflops"], 3), "unit": "TFLOP/s (FP32-equivalent, 2MNK)",
                    "ms_per_step": round(x3["ms_per_step"], 4),
                    "pct_of_bf16_mfma_peak": round(100.0 * 6 * x3["tflops"] / PEAK_BF16, 2),
-                   "pct_of_fp32_peak": round(100.0 * x3["tflops"] / PEAK_FP32, 2),
                    "dominant_tflops": round(x3["dominant_tflops"], 2)},
         "roofline": {
             "bound": "mfma",
@@ -984,6 +1141,16 @@ def main():
         line["bf16x3"]["roofline"]["measured_peak"] = bp
         line["bf16x3"]["roofline"]["frac_of_measured_peak"] = round(
             6 * x3["dominant_tflops"] / bp, 4)
+    if args.workload == "square" and not args.no_extra:
+        del res
+        torch.cuda.empty_cache()
+        res = []
+        cores = len(os.sched_getaffinity(0))
+        line["wide8192"] = wide_object(args, torch, mg, cores)
+        copy = copy_bandwidth(torch)
+        line["hbm_copy"] = copy
+        line["rankk"] = rankk_object(args, torch, mg, copy["gbs"], cores)
+        line["c1"] = c1_object(args, torch, mg)
     if args.workload == "square" and not args.no_batch:
         del res
         torch.cuda.empty_cache()

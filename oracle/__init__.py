@@ -301,7 +301,7 @@ def getrs_f64(*args, **kw):
 
 def hpl_scaled_residual(A: np.ndarray, x: np.ndarray, b: np.ndarray, eps: float) -> float:
     """The residual check of the paper's Linpack run (Section IV-C, Table
-    VI): ||A x - b||_inf / (eps * (||A||_inf * ||x||_inf + ||b||_inf) * N),
+    VII, its footnote): ||A x - b||_inf / (eps * (||A||_inf * ||x||_inf + ||b||_inf) * N),
     evaluated in FP64; A is the dense (n, n) matrix."""
     A = np.asarray(A, dtype=np.float64)
     x = np.asarray(x, dtype=np.float64).reshape(-1)

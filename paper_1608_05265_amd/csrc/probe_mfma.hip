@@ -75,6 +75,36 @@ __global__ __launch_bounds__(256) void probe_f64(const double *ops, float *out, 
     out[blockIdx.x * 256 + threadIdx.x] = (float)s;
 }
 
+// Numerical behaviour of one accumulate: test case t runs exactly one MFMA in
+// one wavefront on operand registers the host laid out per lane (a, b: 64
+// lane vectors per case; c: the 16 (bf16, fp32 32x32) accumulator values of
+// each lane), and stores the 16 results of each lane.  The host compares
+// them with models of the accumulation (one rounding of the exact sum,
+// rounding after every product, ...).
+__global__ __launch_bounds__(64) void probe_round_bf16(const bf16x8 *a, const bf16x8 *b,
+                                                       const float *c, float *out)
+{
+    const int64_t t = blockIdx.x, l = threadIdx.x;
+    floatx16 acc;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[e] = c[(t * 64 + l) * 16 + e];
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[t * 64 + l], b[t * 64 + l], acc, 0, 0, 0);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) out[(t * 64 + l) * 16 + e] = acc[e];
+}
+
+__global__ __launch_bounds__(64) void probe_round_f32(const float *a, const float *b,
+                                                      const float *c, float *out)
+{
+    const int64_t t = blockIdx.x, l = threadIdx.x;
+    floatx16 acc;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[e] = c[(t * 64 + l) * 16 + e];
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[t * 64 + l], b[t * 64 + l], acc, 0, 0, 0);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) out[(t * 64 + l) * 16 + e] = acc[e];
+}
+
 extern "C" {
 
 // kind 0: FP32 MFMA (32x32x2, 4096 flop each), 1: BF16 MFMA (32x32x16,
@@ -94,6 +124,23 @@ int probe_mfma_launch(int kind, const void *ops, float *out, int iters, int bloc
     else
         hipLaunchKernelGGL(probe_f64, dim3(blocks), dim3(256), 0, (hipStream_t)stream,
                            (const double *)ops, out, iters);
+    return (int)hipGetLastError();
+}
+
+// One MFMA per case, `cases` cases: kind 0 = v_mfma_f32_32x32x2_f32 (a, b:
+// cases * 64 floats), kind 1 = v_mfma_f32_32x32x16_bf16 (a, b: cases * 64
+// vectors of 8 bf16); c and out: cases * 64 * 16 floats (lane-major).  Every
+// index stays below these sizes.  Returns a hipError_t.
+int probe_mfma_round(int kind, const void *a, const void *b, const float *c, float *out,
+                     int cases, void *stream)
+{
+    if (cases <= 0 || kind < 0 || kind > 1) return (int)hipErrorInvalidValue;
+    if (kind == 0)
+        hipLaunchKernelGGL(probe_round_f32, dim3(cases), dim3(64), 0, (hipStream_t)stream,
+                           (const float *)a, (const float *)b, c, out);
+    else
+        hipLaunchKernelGGL(probe_round_bf16, dim3(cases), dim3(64), 0, (hipStream_t)stream,
+                           (const bf16x8 *)a, (const bf16x8 *)b, c, out);
     return (int)hipGetLastError();
 }
 

@@ -93,6 +93,10 @@ def _draw(rng: np.random.Generator, size: int, dist: str) -> np.ndarray:
         x = rng.uniform(-1.0, 1.0, size)
     elif dist == "normal":
         x = rng.standard_normal(size)
+    elif dist == "unit":
+        # same sign everywhere: |A||B| = A B, so the bound's denominator is
+        # the result itself and no cancellation hides accumulation error
+        x = rng.uniform(0.0, 1.0, size)
     elif dist == "wide":
         # random sign times 2^u with u continuous uniform in [-8, 8]
         s = np.where(rng.random(size) < 0.5, -1.0, 1.0)

@@ -58,9 +58,16 @@ def test_rankk_full_size(k):
     _free()
 
 
+# Equal measured error (the split form against native FP32 on the same
+# inputs): the split form's maximum and mean normalized error may exceed the
+# native ones by at most this factor.
+EQUAL_ERROR_RATIO = 1.5
+
+
 def test_wide_range_both_forms():
-    """Entries of both signs spread over 2^-8..2^8: both forms within the
-    bound on the same inputs, errors reported side by side."""
+    """Entries of both signs spread over 2^-8..2^8, 8192^3: both forms within
+    the bound on the same inputs, and the split form's maximum and mean
+    normalized error at most EQUAL_ERROR_RATIO times the native form's."""
     p = wl.config4()
     tensors = gu.dev_problem(p)
     stats = {}
@@ -69,6 +76,43 @@ def test_wide_range_both_forms():
         stats[mode] = gu.check_sampled(p, out, count=2048, seed=4, label="wide mode %d" % mode)
     print("wide 8192^3: fp32 max %.3e mean %.3e | bf16x3 max %.3e mean %.3e"
           % (stats[0][0], stats[0][1], stats[1][0], stats[1][1]))
+    assert stats[1][0] <= EQUAL_ERROR_RATIO * stats[0][0], "max error not equal"
+    assert stats[1][1] <= EQUAL_ERROR_RATIO * stats[0][1], "mean error not equal"
+    del tensors
+    _free()
+
+
+def test_same_sign_long_k_every_config():
+    """Entries uniform in [0, 1] (same sign: the bound's denominator equals
+    the result, so no cancellation hides accumulation error) at K = 8192,
+    ragged M and N over several tiles: every compiled configuration of both
+    forms within the bound, and the split form's error equal to the native
+    one's (EQUAL_ERROR_RATIO) configuration by configuration against the
+    native default."""
+    mg = _mg()
+    p = wl.make_problem("N", "N", 300, 270, 8192, 1.0, 0.0, wl.seed_for(8, 1), dist="unit")
+    cref, den = oracle.sgemm_f64(p.transa, p.transb, p.m, p.n, p.k, p.alpha, p.A, p.lda, p.B,
+                                 p.ldb, p.beta, p.C0, p.ldc)
+    tensors = gu.dev_problem(p)
+    native = None
+    worst = {0: 0.0, 1: 0.0}
+    for mode in (0, 1):
+        for cfg in [None] + mg.configs(mode):
+            out = gu.run(p, mode, config_id=None if cfg is None else cfg["id"], tensors=tensors)
+            ok, mx, mean, ratio = oracle.check(gu.c_dense(p, out), cref, den, p.k)
+            name = "default" if cfg is None else cfg["name"]
+            assert ok, "%s mode %d: max/bound %.3e" % (name, mode, ratio)
+            assert gu.padding_untouched(p, out)
+            if mode == 0 and cfg is None:
+                native = (mx, mean)
+            if mode == 1:
+                assert mx <= EQUAL_ERROR_RATIO * native[0], "%s: max %.3e vs native %.3e" % (
+                    name, mx, native[0])
+                assert mean <= EQUAL_ERROR_RATIO * native[1], "%s: mean %.3e vs native %.3e" % (
+                    name, mean, native[1])
+            worst[mode] = max(worst[mode], ratio)
+            print("same-sign K=8192 %s mode %d: max %.3e mean %.3e (%.2e of bound)"
+                  % (name, mode, mx, mean, ratio))
     del tensors
     _free()
 

@@ -28,7 +28,7 @@ def test_lu_pin(o, pin):
 
 
 def test_hpl_residual_formula():
-    """The residual of Table VI on a case worked by hand: A = 2 I (n = 2),
+    """The residual of Table VII's footnote on a case worked by hand: A = 2 I (n = 2),
     x = (1, 1), b = (2, 2.5): ||Ax - b|| = 0.5, ||A|| = 2, ||x|| = 1,
     ||b|| = 2.5, so 0.5 / (eps * (2 + 2.5) * 2)."""
     eps = 2.0 ** -24
