@@ -85,7 +85,14 @@ typedef enum {
  * second kernel adds the partials in split order and applies alpha/beta, so
  * results are reproducible bit for bit).
  * The scratch is allocated on first need and never while the stream is
- * being captured (the call then runs without it).
+ * being captured (the call then runs without it).  When a larger problem
+ * outgrows it, the old buffer is freed after the work queued on the stream
+ * has finished (the call synchronizes that stream once), unless a call
+ * under graph capture used it: a graph may then still reference it, and it
+ * is kept until misgemm_release_workspace().  So a caller that never
+ * captures holds one buffer per (device, stream), the size of its largest
+ * need.  Callers that must not allocate use misgemm_sgemm_ws (caller-owned
+ * workspace) instead.
  */
 int misgemm_sgemm(char transa, char transb, int64_t m, int64_t n, int64_t k,
                   float alpha, const float *A, int64_t lda,
@@ -147,12 +154,16 @@ int misgemm_sgemm_split(char transa, char transb, int64_t m, int64_t n, int64_t 
  * misgemm_sgemm itself, in MISGEMM_BF16X3 mode with a packed configuration
  *   selected, uses a workspace the library owns per (device, stream): grown
  *   with hipMalloc when a larger problem arrives (never while the stream is
- *   being captured; then a non-packed configuration is used instead).
- *   Buffers are kept, including outgrown ones that earlier captured graphs
- *   may still reference, until misgemm_release_workspace().
+ *   being captured; then a non-packed configuration is used instead, and
+ *   misgemm_sgemm_config with an explicit packed configuration returns
+ *   MISGEMM_E_CAPTURING).  Outgrown buffers are freed as described at
+ *   misgemm_sgemm, except those that captured graphs may reference.
  * misgemm_release_workspace: synchronizes the current device and frees the
  *   library-owned scratch of that device (all streams); graphs captured
  *   with it must not be replayed afterwards.
+ * misgemm_workspace_held: bytes of library-owned scratch the current device
+ *   holds (all streams, kept outgrown buffers included); negative status
+ *   when no device is current.
  */
 int64_t misgemm_workspace_size(char transa, char transb, int64_t m, int64_t n, int64_t k,
                                int mode);
@@ -162,6 +173,7 @@ int misgemm_sgemm_ws(char transa, char transb, int64_t m, int64_t n, int64_t k,
                      float beta, float *C, int64_t ldc,
                      int mode, void *workspace, int64_t workspace_bytes, void *stream);
 int misgemm_release_workspace(void);
+int64_t misgemm_workspace_held(void);
 
 /* Description of one compiled kernel configuration. */
 typedef struct {

@@ -18,7 +18,7 @@ import os
 from typing import List, Optional, Sequence
 
 __all__ = ["MisgemmError", "FP32", "BF16X3", "sgemm", "sgemm_config", "sgemm_ws",
-           "workspace_size", "release_workspace", "num_configs",
+           "workspace_size", "release_workspace", "workspace_held", "num_configs",
            "config_info", "configs", "select_config", "load_tuning", "Batch", "bf16x3_split",
            "status_string", "version", "library_path"]
 
@@ -103,6 +103,8 @@ def _load():
     lib.misgemm_workspace_size.restype = i64
     lib.misgemm_release_workspace.argtypes = []
     lib.misgemm_release_workspace.restype = i32
+    lib.misgemm_workspace_held.argtypes = []
+    lib.misgemm_workspace_held.restype = i64
     lib.misgemm_num_configs.argtypes = []
     lib.misgemm_num_configs.restype = i32
     lib.misgemm_config_info.argtypes = [i32, ctypes.POINTER(ConfigDesc)]
@@ -273,6 +275,14 @@ def workspace_size(transa: str, transb: str, m: int, n: int, k: int, mode) -> in
 
 def release_workspace() -> None:
     _check(_load().misgemm_release_workspace(), "misgemm_release_workspace")
+
+
+def workspace_held() -> int:
+    """Bytes of library-owned scratch held on the current device."""
+    rc = _load().misgemm_workspace_held()
+    if rc < 0:
+        raise MisgemmError(int(-rc), "misgemm_workspace_held")
+    return int(rc)
 
 
 def num_configs() -> int:

@@ -170,7 +170,9 @@ int64_t packed_bytes(int64_t m, int64_t n, int64_t k)
 struct StreamWorkspace {
     void *ptr = nullptr;
     int64_t bytes = 0;
-    std::vector<void *> retired;  // outgrown buffers, kept for captured graphs
+    bool captured = false;        // ptr was handed to a call under graph capture
+    std::vector<void *> retired;  // outgrown buffers that captured graphs may reference
+    int64_t retired_bytes = 0;
 };
 std::map<std::pair<int, void *>, StreamWorkspace> g_ws;
 std::mutex g_ws_mutex;
@@ -182,26 +184,51 @@ bool capturing(hipStream_t s)
 }
 
 // Library-owned workspace of at least `bytes` for the current device and
-// stream `s`, or nullptr when it would have to grow while `s` is capturing or
-// the allocation fails.
-void *library_workspace(int64_t bytes, hipStream_t s)
+// stream `s`.  Returns 0 and the buffer, MISGEMM_E_CAPTURING when it would
+// have to grow while `s` is capturing, or the HIP error of a failed
+// allocation.  An outgrown buffer is freed once the work queued on `s` has
+// finished, unless it was handed to a call under capture: then a graph may
+// still use it and it is kept until misgemm_release_workspace, so memory
+// accumulates only across growths that follow captures.
+int library_workspace(int64_t bytes, hipStream_t s, void **out)
 {
+    *out = nullptr;
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    if (hipGetDevice(&dev) != hipSuccess) return MISGEMM_E_NO_DEVICE;
     std::lock_guard<std::mutex> lock(g_ws_mutex);
     StreamWorkspace &w = g_ws[{dev, (void *)s}];
-    if (w.bytes >= bytes) return w.ptr;
-    if (capturing(s)) return nullptr;
-    const int64_t want = std::max<int64_t>(bytes, w.bytes + w.bytes / 2);
-    void *p = nullptr;
-    if (hipMalloc(&p, (size_t)want) != hipSuccess) {
-        (void)hipGetLastError();
-        return nullptr;
+    const bool cap = capturing(s);
+    if (w.bytes >= bytes) {
+        if (cap) w.captured = true;
+        *out = w.ptr;
+        return 0;
     }
-    if (w.ptr) w.retired.push_back(w.ptr);
+    if (cap) return MISGEMM_E_CAPTURING;
+    const int64_t want = std::max<int64_t>(bytes, w.bytes + w.bytes / 2);
+    if (w.ptr) {
+        if (w.captured) {
+            w.retired.push_back(w.ptr);
+            w.retired_bytes += w.bytes;
+        } else {
+            // only calls on `s` use it, and they run in order
+            hipError_t e = hipStreamSynchronize(s);
+            if (e == hipSuccess) e = hipFree(w.ptr);
+            if (e != hipSuccess) return (int)e;
+        }
+        w.ptr = nullptr;
+        w.bytes = 0;
+        w.captured = false;
+    }
+    void *p = nullptr;
+    const hipError_t e = hipMalloc(&p, (size_t)want);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return (int)e;
+    }
     w.ptr = p;
     w.bytes = want;
-    return p;
+    *out = p;
+    return 0;
 }
 
 hipError_t launch_packed_path(const ConfigEntry &cfg, int ta, int tb, const GemmArgs &g,
@@ -269,7 +296,8 @@ GemmArgs make_args(int64_t m, int64_t n, int64_t k, float alpha, const float *A,
     return g;
 }
 
-// Workspace policy of one call.
+// Workspace policy of one call: library scratch grown on demand, a caller's
+// workspace, or none.
 enum WsPolicy { WS_LIBRARY, WS_CALLER, WS_NONE };
 
 // Split-K factor for a non-packed configuration when neither the caller nor
@@ -330,10 +358,13 @@ int run_sgemm(char transa, char transb, int64_t m, int64_t n, int64_t k, float a
     if (table[cfg].desc.packed) {
         if (pack_kblocks(k) > 65535) return MISGEMM_E_TOO_LARGE;
         const int64_t need = packed_bytes(m, n, k);
+        int wrc = 0;
         if (policy == WS_CALLER) ws = workspace;
-        else if (policy == WS_LIBRARY) ws = library_workspace(need, s);
+        else if (policy == WS_LIBRARY) wrc = library_workspace(need, s, &ws);
         if (ws == nullptr) {
-            if (config_id >= 0 && policy == WS_LIBRARY && !packable) return MISGEMM_E_CAPTURING;
+            // an explicitly requested packed configuration runs packed or not at all
+            if (config_id >= 0 && policy == WS_LIBRARY) return wrc != 0 ? wrc : MISGEMM_E_CAPTURING;
+            if (wrc != 0 && wrc != MISGEMM_E_CAPTURING) return wrc;
             // no workspace (capturing, or none given): a non-packed config
             cfg = heuristic_config(mode, m, n, k, dev->cus, false);
             gm = group_m > 0 ? group_m : GROUP_M_DEFAULT;
@@ -351,15 +382,17 @@ int run_sgemm(char transa, char transb, int64_t m, int64_t n, int64_t k, float a
     splits = effective_splits(k, d.bk, splits);
     if (splits > 1) {
         if (e.splitk[0][0] == nullptr) return MISGEMM_E_BAD_CONFIG;
-        float *part = nullptr;
-        if (policy == WS_LIBRARY)
-            part = (float *)library_workspace(splits * tiles * d.bm * d.bn * 4, s);
+        const int64_t need = (int64_t)splits * tiles * d.bm * d.bn * 4;
+        void *part = nullptr;
+        int wrc = 0;
+        if (policy == WS_LIBRARY) wrc = library_workspace(need, s, &part);
         if (part != nullptr) {
-            g.part = part;
+            g.part = (float *)part;
             g.splits = splits;
             return (int)e.splitk[ta][tb](g, gm, s);
         }
-        if (forced) return MISGEMM_E_CAPTURING;
+        if (forced) return wrc != 0 ? wrc : MISGEMM_E_CAPTURING;
+        if (wrc != 0 && wrc != MISGEMM_E_CAPTURING) return wrc;
     }
     return (int)e.launch[ta][tb](g, gm, s);
 }
@@ -565,6 +598,17 @@ int misgemm_sgemm_split(char transa, char transb, int64_t m, int64_t n, int64_t 
                      config_id, group_m, stream, WS_LIBRARY, nullptr, 0, splits);
 }
 
+int64_t misgemm_workspace_held(void)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return -(int64_t)MISGEMM_E_NO_DEVICE;
+    std::lock_guard<std::mutex> lock(g_ws_mutex);
+    int64_t held = 0;
+    for (const auto &kv : g_ws)
+        if (kv.first.first == dev) held += kv.second.bytes + kv.second.retired_bytes;
+    return held;
+}
+
 int misgemm_dgemm(char transa, char transb, int64_t m, int64_t n, int64_t k, double alpha,
                   const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
                   double *C, int64_t ldc, int dmode, void *stream)
@@ -603,8 +647,9 @@ int misgemm_dgemm(char transa, char transb, int64_t m, int64_t n, int64_t k, dou
     // with alpha and beta applied in FP64.
     const int64_t na = lda * (acols - 1) + arows, nb = ldb * (bcols - 1) + brows;
     const int64_t a_bytes = (na * 4 + 255) / 256 * 256, b_bytes = (nb * 4 + 255) / 256 * 256;
-    char *ws = (char *)library_workspace(a_bytes + b_bytes + m * n * 4, s);
-    if (ws == nullptr) return MISGEMM_E_CAPTURING;
+    char *ws = nullptr;
+    rc = library_workspace(a_bytes + b_bytes + m * n * 4, s, (void **)&ws);
+    if (rc != 0) return rc;
     float *a32 = (float *)ws, *b32 = (float *)(ws + a_bytes), *p32 = (float *)(ws + a_bytes + b_bytes);
     hipError_t e = launch_narrow(A, na, a32, s);
     if (e == hipSuccess) e = launch_narrow(B, nb, b32, s);

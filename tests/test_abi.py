@@ -208,13 +208,7 @@ def test_header_is_plain_c(tmp_path):
     if cc is None:
         pytest.skip("no C compiler")
     inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
-    names = ["misgemm_sgemm", "misgemm_sgemm_config", "misgemm_sgemm_split", "misgemm_sgemm_ws",
-             "misgemm_workspace_size", "misgemm_release_workspace", "misgemm_num_configs",
-             "misgemm_config_info", "misgemm_select_config", "misgemm_load_tuning",
-             "misgemm_batch_plan", "misgemm_batch_launch", "misgemm_batch_info",
-             "misgemm_batch_destroy", "misgemm_dgemm", "misgemm_sgetrf", "misgemm_sgetrs",
-             "misgemm_sgemm_host", "misgemm_dgemm_host", "sgemm_", "dgemm_",
-             "misgemm_bf16x3_split", "misgemm_status_string", "misgemm_version"]
+    names = header_functions() + ["sgemm_", "dgemm_"]
     src = tmp_path / "use.c"
     src.write_text('#include "misgemm.h"\nvoid *entry_points[] = {%s};\n'
                    % ", ".join("(void *)&%s" % n for n in names))

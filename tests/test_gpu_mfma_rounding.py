@@ -32,6 +32,15 @@ pytestmark = pytest.mark.gpu
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
+# Largest error of one v_mfma_f32_32x32x16_bf16 accumulate, in units of
+# u = 2^-24 times |c| + sum_k |a_k b_k|, that the split form's accuracy
+# argument allows for (measured: 2.74 over about 3000 crafted, adversarial and
+# random cases).  With N = 6 * ceil(K/16) accumulates per output and the
+# dropped part products (at most (2 + 2^-8) u |a||b| each), the split form's
+# error is at most (1.008 * KAPPA_BF16 * N + 2.004 + 3) u times the bound's
+# denominator, within 2 K u for K >= 21 and 12 <= K <= 16.
+KAPPA_BF16 = 3.0
+
 
 def _probe_lib():
     lib = ctypes.CDLL(os.path.join(ROOT, "paper_1608_05265_amd", "libmisgemm_probe.so"))
@@ -217,5 +226,19 @@ def test_mfma_accumulate_rounding(kind):
         json.dump(s, f, indent=1)
     print(json.dumps(s))
     assert math.isfinite(s["max_err_u"])
-    # at most one rounding per addend (17 for bf16, 3 for fp32)
-    assert s["max_err_u"] <= (17 if kind == 1 else 3)
+    # no bias where the accumulator dominates: the adder rounds to nearest
+    # (a truncating adder would drift toward zero on same-sign data)
+    assert abs(s["acc_dominated_mean_signed_err_u"]) < 0.1
+    if kind == 0:
+        # the FP32 instruction is a chain of fused multiply-adds in k order:
+        # c, then + a_0 b_0, then + a_1 b_1, each rounded to nearest even
+        assert s["models_matched"]["seq"] == s["cases"]
+        assert s["max_err_u"] <= 2.0
+    else:
+        # the BF16 instruction does not round after every product: sixteen
+        # half-ulp products of 1 survive (1 + 2^-20, not 1) ...
+        c0, d0, ex0 = s["crafted"][0]
+        assert d0 == ex0 == 1.0 + 2.0 ** -20
+        # ... and one accumulate errs by at most KAPPA_BF16 u (|c| + sum |p|),
+        # the figure the single-accumulator bound of the split form rests on
+        assert s["max_err_u"] <= KAPPA_BF16
