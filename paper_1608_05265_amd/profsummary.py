@@ -3,6 +3,7 @@
     python -m paper_1608_05265_amd.profsummary trace <dir-with-kernel_trace.csv>
     python -m paper_1608_05265_amd.profsummary pmc <dir-with-counter_collection.csv>
     python -m paper_1608_05265_amd.profsummary dispatch <dir-with-counter_collection.csv>
+    python -m paper_1608_05265_amd.profsummary bytes <read-dir> <write-dir>
 
 `trace` groups dispatches by kernel and grid size and prints calls, average,
 minimum and maximum duration in microseconds; `pmc` prints the per-dispatch
@@ -12,7 +13,8 @@ matrix-core busy fraction busy / (SIMDs * GRBM_GUI_ACTIVE / XCDs) (the busy
 counter sums the cycles of every SIMD, GRBM_GUI_ACTIVE sums the active
 cycles of the 8 XCDs; 1024 SIMDs on MI355X); `dispatch` prints every
 dispatch with its counters (for calibration runs that mix kernels of one
-name).
+name); `bytes` turns the L2-to-memory request counters of two runs into
+bytes per dispatch (below).
 Kernel names are shortened to the template arguments that identify a tile
 configuration.
 """
@@ -126,8 +128,67 @@ def dispatch(d: str):
     return "\n".join(out)
 
 
+# Bytes that leave the L2 (the TCC/EA interface), counted by request size:
+# reads 128 * TCC_EA0_RDREQ_128B + 64 * TCC_EA0_RDREQ_64B + 32 * TCC_EA0_RDREQ_32B,
+# of which 32 * TCC_EA0_RDREQ_DRAM_32B go to the memory controller (DRAM: the
+# Infinity Cache and HBM behind it; the rest goes to GMI/IO); writes
+# 64 * TCC_EA0_WRREQ_64B + 32 * (TCC_EA0_WRREQ - TCC_EA0_WRREQ_64B), of which
+# 32 * TCC_EA0_WRREQ_WRITE_DRAM_32B go to the memory controller.  (The
+# FETCH_SIZE expression of this rocprofv3 prices 128-byte reads through
+# TCC_BUBBLE, which reads 0 on gfx950, so it counts them as 64 bytes.)
+READ_COUNTERS = ["TCC_EA0_RDREQ_32B_sum", "TCC_EA0_RDREQ_64B_sum", "TCC_EA0_RDREQ_128B_sum",
+                 "TCC_EA0_RDREQ_DRAM_32B_sum"]
+WRITE_COUNTERS = ["TCC_EA0_WRREQ_sum", "TCC_EA0_WRREQ_64B_sum",
+                  "TCC_EA0_WRREQ_WRITE_DRAM_32B_sum"]
+
+
+def _per_dispatch(d: str):
+    rows = list(csv.DictReader(open(_find(d, "counter_collection.csv"))))
+    per = collections.OrderedDict()
+    for r in rows:
+        key = int(r["Dispatch_Id"])
+        per.setdefault(key, [short_name(r["Kernel_Name"]), r.get("Grid_Size", "?"),
+                             collections.defaultdict(float)])
+        name = r["Counter_Name"]
+        per[key][2][name] += float(r["Counter_Value"])
+    return per
+
+
+def read_bytes(c) -> tuple:
+    total = (128.0 * c["TCC_EA0_RDREQ_128B_sum"] + 64.0 * c["TCC_EA0_RDREQ_64B_sum"] +
+             32.0 * c["TCC_EA0_RDREQ_32B_sum"])
+    return total, 32.0 * c["TCC_EA0_RDREQ_DRAM_32B_sum"]
+
+
+def write_bytes(c) -> tuple:
+    w64 = c["TCC_EA0_WRREQ_64B_sum"]
+    total = 64.0 * w64 + 32.0 * (c["TCC_EA0_WRREQ_sum"] - w64)
+    return total, 32.0 * c["TCC_EA0_WRREQ_WRITE_DRAM_32B_sum"]
+
+
+def bytes_summary(read_dir: str, write_dir: str):
+    """Per (kernel, grid): mean L2-to-memory read and write bytes per
+    dispatch (all, and the part sent to the memory controller)."""
+    groups = collections.OrderedDict()
+    for d, fn, slot in ((read_dir, read_bytes, 0), (write_dir, write_bytes, 1)):
+        for name, grid, c in _per_dispatch(d).values():
+            g = groups.setdefault((name, grid), [[], []])
+            g[slot].append(fn(c))
+    out = ["%-58s %-10s %5s %12s %12s %5s %12s %12s" % (
+        "kernel", "grid", "nrd", "read_B", "read_dram_B", "nwr", "write_B", "write_dram_B")]
+    for (k, g), (rd, wr) in groups.items():
+        def mean(v, i):
+            return sum(x[i] for x in v) / len(v) if v else float("nan")
+        out.append("%-58s %-10s %5d %12.4e %12.4e %5d %12.4e %12.4e" % (
+            k, g, len(rd), mean(rd, 0), mean(rd, 1), len(wr), mean(wr, 0), mean(wr, 1)))
+    return "\n".join(out)
+
+
 def main(argv=None):
     argv = sys.argv[1:] if argv is None else argv
+    if len(argv) == 3 and argv[0] == "bytes":
+        print(bytes_summary(argv[1], argv[2]))
+        return 0
     if len(argv) != 2 or argv[0] not in ("trace", "pmc", "dispatch"):
         print(__doc__)
         return 2
