@@ -63,6 +63,7 @@ typedef enum {
 #define MISGEMM_E_BATCH            1004 /* bad batch (see bad_index)             */
 #define MISGEMM_E_NULL_PLAN        1005 /* plan pointer is NULL                  */
 #define MISGEMM_E_TOO_LARGE        1006 /* a size exceeds what the kernels index */
+#define MISGEMM_E_SCRATCH          1007 /* needs more than the static scratch    */
 
 /*
  * C = alpha * op(A) * op(B) + beta * C  (Section III-A).
@@ -133,6 +134,29 @@ int misgemm_sgemm_split(char transa, char transb, int64_t m, int64_t n, int64_t 
                         const float *B, int64_t ldb,
                         float beta, float *C, int64_t ldc,
                         int mode, int config_id, int group_m, int splits, void *stream);
+
+/*
+ * For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the call of
+ * misgemm_sgemm_split (same arguments, errors and results bit for bit) with
+ * its split-K partial tiles in a static device array of
+ * MISGEMM_STATIC_SCRATCH_BYTES that the library holds on every device it
+ * runs on until the process ends.  Allocates nothing and frees nothing.
+ * splits * tiles * bm * bn * 4 bytes must fit the array, else
+ * MISGEMM_E_SCRATCH (nothing launched); a packed configuration is refused
+ * (-15: its panels do not fit).  The array needs no clearing: every partial
+ * tile is written before it is read.  Every call on one device shares that
+ * device's array: calls that overlap in time on one GPU (other streams,
+ * concurrently replayed graphs) race on it; calls on one stream run in
+ * order and are safe.  The first call on each device looks the array's
+ * address up (hipGetSymbolAddress); make it outside graph capture.
+ */
+#define MISGEMM_STATIC_SCRATCH_BYTES (64LL << 20)
+int misgemm_sgemm_split_noalloc(char transa, char transb, int64_t m, int64_t n, int64_t k,
+                                float alpha, const float *A, int64_t lda,
+                                const float *B, int64_t ldb,
+                                float beta, float *C, int64_t ldc,
+                                int mode, int config_id, int group_m, int splits, void *stream);
 
 /*
  * Workspace for the packed bf16x3 path.  Packed configurations first split

@@ -18,6 +18,7 @@ import os
 from typing import List, Optional, Sequence
 
 __all__ = ["MisgemmError", "FP32", "BF16X3", "sgemm", "sgemm_config", "sgemm_ws",
+           "sgemm_split", "sgemm_split_noalloc",
            "workspace_size", "release_workspace", "workspace_held", "num_configs",
            "config_info", "configs", "select_config", "load_tuning", "Batch", "bf16x3_split",
            "status_string", "version", "library_path"]
@@ -97,6 +98,8 @@ def _load():
     lib.misgemm_sgetrs.restype = i32
     lib.misgemm_sgemm_split.argtypes = sig + [i32, i32, i32, vp]
     lib.misgemm_sgemm_split.restype = i32
+    lib.misgemm_sgemm_split_noalloc.argtypes = sig + [i32, i32, i32, vp]
+    lib.misgemm_sgemm_split_noalloc.restype = i32
     lib.misgemm_sgemm_ws.argtypes = sig + [vp, i64, vp]
     lib.misgemm_sgemm_ws.restype = i32
     lib.misgemm_workspace_size.argtypes = [c, c, i64, i64, i64, i32]
@@ -254,6 +257,20 @@ def sgemm_split(transa: str, transb: str, m: int, n: int, k: int, alpha: float, 
                                      lda, _ptr(B), ldb, beta, _ptr(C), ldc, _mode(mode),
                                      config_id, group_m, splits, _stream(stream))
     _check(rc, "misgemm_sgemm_split")
+
+
+def sgemm_split_noalloc(transa: str, transb: str, m: int, n: int, k: int, alpha: float, A,
+                        lda: int, B, ldb: int, beta: float, C, ldc: int, mode,
+                        config_id: int = -1, group_m: int = 0, splits: int = 1,
+                        stream=None) -> None:
+    """sgemm_split with the partial tiles in the library's static device
+    array: allocates nothing (for graph capture and callers that cannot
+    allocate)."""
+    rc = _load().misgemm_sgemm_split_noalloc(transa.encode(), transb.encode(), m, n, k, alpha,
+                                             _ptr(A), lda, _ptr(B), ldb, beta, _ptr(C), ldc,
+                                             _mode(mode), config_id, group_m, splits,
+                                             _stream(stream))
+    _check(rc, "misgemm_sgemm_split_noalloc")
 
 
 def sgemm_ws(transa: str, transb: str, m: int, n: int, k: int, alpha: float, A, lda: int, B,

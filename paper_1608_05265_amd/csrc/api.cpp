@@ -231,6 +231,37 @@ int library_workspace(int64_t bytes, hipStream_t s, void **out)
     return 0;
 }
 
+// ---------------------------------------------------------------------------
+// Static scratch of misgemm_sgemm_split_noalloc: one array per device, in
+// the code object, so that calls need no allocation.  Host code uses the
+// device address hipGetSymbolAddress returns for the current device, never
+// the array's name (a host-side stand-in).
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) float scratch[MISGEMM_STATIC_SCRATCH_BYTES / 4];
+void *g_scratch_ptr[MAX_DEVICES];
+std::mutex g_scratch_mutex;
+
+// Device address of the current device's copy of `scratch`, looked up once
+// per device.
+int static_scratch(void **out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES)
+        return MISGEMM_E_NO_DEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr) {
+            (void)hipGetLastError();
+            return e != hipSuccess ? (int)e : MISGEMM_E_NO_DEVICE;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return 0;
+}
+
 hipError_t launch_packed_path(const ConfigEntry &cfg, int ta, int tb, const GemmArgs &g,
                               void *ws, int group_m, hipStream_t s)
 {
@@ -297,8 +328,9 @@ GemmArgs make_args(int64_t m, int64_t n, int64_t k, float alpha, const float *A,
 }
 
 // Workspace policy of one call: library scratch grown on demand, a caller's
-// workspace, or none.
-enum WsPolicy { WS_LIBRARY, WS_CALLER, WS_NONE };
+// workspace, none, or the static scratch (split-K partials only, at most
+// MISGEMM_STATIC_SCRATCH_BYTES).
+enum WsPolicy { WS_LIBRARY, WS_CALLER, WS_NONE, WS_STATIC };
 
 // Split-K factor for a non-packed configuration when neither the caller nor
 // the tuning table fixed one: only when the tiles leave CUs idle, enough
@@ -346,7 +378,7 @@ int run_sgemm(char transa, char transb, int64_t m, int64_t n, int64_t k, float a
     if (alpha == 0.0f || k == 0) return (int)launch_scale(beta, C, m, n, ldc, s);
     const int ta = trans_flag(transa), tb = trans_flag(transb);
     int gm = group_m > 0 ? group_m : GROUP_M_DEFAULT;
-    const bool packable = mode == MISGEMM_BF16X3 && policy != WS_NONE &&
+    const bool packable = mode == MISGEMM_BF16X3 && policy != WS_NONE && policy != WS_STATIC &&
                           pack_kblocks(k) <= 65535;
     int cfg = config_id;
     int splits = splits_req;
@@ -357,6 +389,7 @@ int run_sgemm(char transa, char transb, int64_t m, int64_t n, int64_t k, float a
     void *ws = nullptr;
     if (table[cfg].desc.packed) {
         if (pack_kblocks(k) > 65535) return MISGEMM_E_TOO_LARGE;
+        if (policy == WS_STATIC) return -15;
         const int64_t need = packed_bytes(m, n, k);
         int wrc = 0;
         if (policy == WS_CALLER) ws = workspace;
@@ -385,7 +418,12 @@ int run_sgemm(char transa, char transb, int64_t m, int64_t n, int64_t k, float a
         const int64_t need = (int64_t)splits * tiles * d.bm * d.bn * 4;
         void *part = nullptr;
         int wrc = 0;
-        if (policy == WS_LIBRARY) wrc = library_workspace(need, s, &part);
+        if (policy == WS_LIBRARY) {
+            wrc = library_workspace(need, s, &part);
+        } else if (policy == WS_STATIC) {
+            if (need > ws_bytes) return MISGEMM_E_SCRATCH;
+            part = workspace;
+        }
         if (part != nullptr) {
             g.part = (float *)part;
             g.splits = splits;
@@ -596,6 +634,36 @@ int misgemm_sgemm_split(char transa, char transb, int64_t m, int64_t n, int64_t 
     }
     return run_sgemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, mode,
                      config_id, group_m, stream, WS_LIBRARY, nullptr, 0, splits);
+}
+
+int misgemm_sgemm_split_noalloc(char transa, char transb, int64_t m, int64_t n, int64_t k,
+                                float alpha, const float *A, int64_t lda, const float *B,
+                                int64_t ldb, float beta, float *C, int64_t ldc, int mode,
+                                int config_id, int group_m, int splits, void *stream)
+{
+    if (group_m < 0 || group_m > 4096) return -16;
+    if (splits < 1 || splits > 64) return -17;
+    const auto &t = configs();
+    if (config_id >= 0 && config_id < (int)t.size() && t[config_id].desc.packed) return -15;
+    if (config_id < 0 && splits > 1) {
+        int64_t best = INT64_MAX;
+        for (size_t i = 0; i < t.size(); ++i) {
+            const int64_t area = (int64_t)t[i].desc.bm * t[i].desc.bn;
+            if (t[i].desc.mode == mode && t[i].splitk[0][0] && area < best) {
+                best = area;
+                config_id = (int)i;
+            }
+        }
+    }
+    // argument errors first, so that C stays untouched on any of them
+    int rc = validate(transa, transb, m, n, k, alpha, A, lda, B, ldb, C, ldc, mode);
+    if (rc != 0) return rc;
+    void *ptr = nullptr;
+    rc = static_scratch(&ptr);
+    if (rc != 0) return rc;
+    return run_sgemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, mode,
+                     config_id, group_m, stream, WS_STATIC, ptr, MISGEMM_STATIC_SCRATCH_BYTES,
+                     splits);
 }
 
 int64_t misgemm_workspace_held(void)
@@ -989,6 +1057,8 @@ const char *misgemm_status_string(int status)
     case MISGEMM_E_BATCH: return "invalid batch description";
     case MISGEMM_E_NULL_PLAN: return "batch plan pointer is NULL";
     case MISGEMM_E_TOO_LARGE: return "a size exceeds the supported range";
+    case MISGEMM_E_SCRATCH:
+        return "split-K partial tiles exceed the static scratch (MISGEMM_STATIC_SCRATCH_BYTES)";
     default: break;
     }
     if (status < 1000) {
