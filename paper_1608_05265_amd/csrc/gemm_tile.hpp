@@ -874,6 +874,241 @@ struct X3PTile {
 };
 
 // ---------------------------------------------------------------------------
+// Small tiles for grids that leave CUs idle (a 256^3 problem has 16 tiles of
+// 64x64): every one of KW waves holds the whole BM x BN tile and takes every
+// KW-th K step of each staged block, so a tile's MFMA chain is KW times
+// shorter; at the end the waves' accumulators are added in wave order
+// through LDS and wave 0 stores.  The partial sums of one element therefore
+// run over the k steps s = w (mod KW) of wave w, and the result is the same
+// bits for every launch.
+// ---------------------------------------------------------------------------
+template <int BM_, int BN_, int BK_, int KW_>
+struct WShape {
+    static constexpr int BM = BM_, BN = BN_, BK = BK_, KW = KW_, OCC = 1;
+    static constexpr int WM = BM, WN = BN, NWM = 1, NWN = 1, NW = KW, NT = 64 * KW;
+    static constexpr int RM = BM / 32, RN = BN / 32;
+    static_assert(BM % 32 == 0 && BN % 32 == 0, "the tile is made of 32x32 blocks");
+};
+
+// Waves 1..KW-1 post their accumulators to LDS (lane-contiguous, so every
+// store and load of a wave is conflict-free), wave 0 adds them in wave
+// order.  The caller's K loop ended with a barrier, so the staging buffers
+// are free.
+template <int KW, int RM, int RN>
+__device__ __forceinline__ void wave_sum(floatx16 (&acc)[RM][RN], float *lds, int wave,
+                                         int lane)
+{
+    constexpr int PER = RM * RN * 16 * 64;
+    if (wave > 0) {
+        float *dst = lds + (wave - 1) * PER;
+#pragma unroll
+        for (int i = 0; i < RM; ++i)
+#pragma unroll
+            for (int j = 0; j < RN; ++j)
+#pragma unroll
+                for (int e = 0; e < 16; ++e) dst[((i * RN + j) * 16 + e) * 64 + lane] = acc[i][j][e];
+    }
+    __syncthreads();
+    if (wave == 0) {
+        for (int w = 1; w < KW; ++w) {
+            const float *src = lds + (w - 1) * PER;
+#pragma unroll
+            for (int i = 0; i < RM; ++i)
+#pragma unroll
+                for (int j = 0; j < RN; ++j)
+#pragma unroll
+                    for (int e = 0; e < 16; ++e)
+                        acc[i][j][e] += src[((i * RN + j) * 16 + e) * 64 + lane];
+        }
+    }
+}
+
+template <class SH, bool TA, bool TB>
+struct F32WTile {
+    using SA = StageF32<SH::BM, SH::BK, SH::NT, TA>;
+    using SB = StageF32<SH::BN, SH::BK, SH::NT, !TB>;
+    static constexpr int KW = SH::KW, RM = SH::RM, RN = SH::RN, NT = SH::NT;
+    static constexpr int STEPS = SH::BK / 2;  // two k per v_mfma_f32_32x32x2_f32
+    static_assert(STEPS % KW == 0, "every wave takes the same number of k steps");
+    static constexpr int STAGE_FLOATS = SA::FLOATS + SB::FLOATS;
+    static constexpr int RED_FLOATS = (KW - 1) * RM * RN * 16 * 64;
+    static constexpr int LDS_BYTES =
+        (2 * STAGE_FLOATS > RED_FLOATS ? 2 * STAGE_FLOATS : RED_FLOATS) * 4;
+
+    template <bool SPLIT = false>
+    __device__ __forceinline__ static void run(const GemmArgs &g, int64_t m0, int64_t n0,
+                                               char *smem)
+    {
+        static_assert(!SPLIT, "no split-K variant");
+        const bool fast = m0 + SH::BM <= g.m && n0 + SH::BN <= g.n && g.k % SH::BK == 0 &&
+                          (g.vec_a || !SA::NEEDS_VEC) && (g.vec_b || !SB::NEEDS_VEC);
+        if (fast) run_impl<true>(g, m0, n0, smem);
+        else run_impl<false>(g, m0, n0, smem);
+    }
+
+    template <bool FAST>
+    __device__ __forceinline__ static void run_impl(const GemmArgs &g, int64_t m0, int64_t n0,
+                                                    char *smem)
+    {
+        float *lds = reinterpret_cast<float *>(smem);
+        const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+        const int half = lane >> 5, l32 = lane & 31;
+        floatx16 acc[RM][RN];
+#pragma unroll
+        for (int i = 0; i < RM; ++i)
+#pragma unroll
+            for (int j = 0; j < RN; ++j)
+#pragma unroll
+                for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
+        const int64_t ktiles = (g.k + SH::BK - 1) / SH::BK;
+        SA sa;
+        SB sb;
+        if (ktiles > 0) {
+            sa.template load<FAST>(g.A, g.lda, m0, 0, g.m, g.k, g.vec_a, tid);
+            sb.template load<FAST>(g.B, g.ldb, n0, 0, g.n, g.k, g.vec_b, tid);
+            sa.store(lds, tid);
+            sb.store(lds + SA::FLOATS, tid);
+        }
+        __syncthreads();
+        for (int64_t kt = 0; kt < ktiles; ++kt) {
+            float *cur = lds + (kt & 1) * STAGE_FLOATS;
+            float *nxt = lds + ((kt + 1) & 1) * STAGE_FLOATS;
+            const bool more = kt + 1 < ktiles;
+            if (more) {
+                const int64_t k0 = (kt + 1) * SH::BK;
+                sa.template load<FAST>(g.A, g.lda, m0, k0, g.m, g.k, g.vec_a, tid);
+                sb.template load<FAST>(g.B, g.ldb, n0, k0, g.n, g.k, g.vec_b, tid);
+            }
+            const float *As = cur + l32;
+            const float *Bs = cur + SA::FLOATS + l32;
+#pragma unroll
+            for (int s = 0; s < STEPS / KW; ++s) {
+                const int kr = 2 * (s * KW + wave) + half;  // lanes 0-31: even k, 32-63: odd k
+                float a[RM], b[RN];
+#pragma unroll
+                for (int i = 0; i < RM; ++i) a[i] = As[kr * SA::LD + i * 32];
+#pragma unroll
+                for (int j = 0; j < RN; ++j) b[j] = Bs[kr * SB::LD + j * 32];
+#pragma unroll
+                for (int i = 0; i < RM; ++i)
+#pragma unroll
+                    for (int j = 0; j < RN; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[j], acc[i][j],
+                                                                          0, 0, 0);
+            }
+            if (more) {
+                sa.store(nxt, tid);
+                sb.store(nxt + SA::FLOATS, tid);
+            }
+            __syncthreads();
+        }
+        wave_sum<KW, RM, RN>(acc, lds, wave, lane);
+        if (wave == 0) epilogue<RM, RN>(g, acc, m0, n0, lane);
+    }
+};
+
+// The split form of the small tile: each K block holds KW steps of 16 k,
+// one per wave, split while staged; a wave adds its six part products
+// smallest first into one accumulator, as the large split-form tiles do.
+template <class SH, bool TA, bool TB>
+struct X3WTile {
+    using SA = StageX3<SH::BM, SH::BK, SH::NT, TA>;
+    using SB = StageX3<SH::BN, SH::BK, SH::NT, !TB>;
+    static constexpr int KW = SH::KW, RM = SH::RM, RN = SH::RN, NT = SH::NT;
+    static constexpr int STEPS = SH::BK / 16;  // 16 k per v_mfma_f32_32x32x16_bf16
+    static_assert(STEPS % KW == 0, "every wave takes the same number of k steps");
+    static constexpr int STAGE_HALVES = SA::HALVES + SB::HALVES;
+    static constexpr int RED_FLOATS = (KW - 1) * RM * RN * 16 * 64;
+    static constexpr int LDS_BYTES =
+        (2 * STAGE_HALVES * 2 > RED_FLOATS * 4 ? 2 * STAGE_HALVES * 2 : RED_FLOATS * 4);
+
+    template <bool SPLIT = false>
+    __device__ __forceinline__ static void run(const GemmArgs &g, int64_t m0, int64_t n0,
+                                               char *smem)
+    {
+        static_assert(!SPLIT, "no split-K variant");
+        const bool fast = m0 + SH::BM <= g.m && n0 + SH::BN <= g.n && g.k % SH::BK == 0 &&
+                          (g.vec_a || !SA::NEEDS_VEC) && (g.vec_b || !SB::NEEDS_VEC);
+        if (fast) run_impl<true>(g, m0, n0, smem);
+        else run_impl<false>(g, m0, n0, smem);
+    }
+
+    template <bool FAST>
+    __device__ __forceinline__ static void run_impl(const GemmArgs &g, int64_t m0, int64_t n0,
+                                                    char *smem)
+    {
+        __bf16 *lds = reinterpret_cast<__bf16 *>(smem);
+        const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+        const int half = lane >> 5, l32 = lane & 31;
+        floatx16 acc[RM][RN];
+#pragma unroll
+        for (int i = 0; i < RM; ++i)
+#pragma unroll
+            for (int j = 0; j < RN; ++j)
+#pragma unroll
+                for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
+        const int64_t ktiles = (g.k + SH::BK - 1) / SH::BK;
+        SA sa;
+        SB sb;
+        if (ktiles > 0) {
+            sa.template load<FAST>(g.A, g.lda, m0, 0, g.m, g.k, g.vec_a, tid);
+            sb.template load<FAST>(g.B, g.ldb, n0, 0, g.n, g.k, g.vec_b, tid);
+            sa.store(lds, tid);
+            sb.store(lds + SA::HALVES, tid);
+        }
+        __syncthreads();
+        for (int64_t kt = 0; kt < ktiles; ++kt) {
+            __bf16 *cur = lds + (kt & 1) * STAGE_HALVES;
+            __bf16 *nxt = lds + ((kt + 1) & 1) * STAGE_HALVES;
+            const bool more = kt + 1 < ktiles;
+            if (more) {
+                const int64_t k0 = (kt + 1) * SH::BK;
+                sa.template load<FAST>(g.A, g.lda, m0, k0, g.m, g.k, g.vec_a, tid);
+                sb.template load<FAST>(g.B, g.ldb, n0, k0, g.n, g.k, g.vec_b, tid);
+            }
+            const __bf16 *As = cur + l32 * SA::LD + half * 8;
+            const __bf16 *Bs = cur + SA::HALVES + l32 * SB::LD + half * 8;
+#pragma unroll
+            for (int s = 0; s < STEPS / KW; ++s) {
+                const int ks = s * KW + wave;
+                bf16x8 a[RM][3], b[RN][3];
+#pragma unroll
+                for (int i = 0; i < RM; ++i)
+#pragma unroll
+                    for (int t = 0; t < 3; ++t)
+                        a[i][t] = *reinterpret_cast<const bf16x8 *>(
+                            As + t * SA::PART + i * 32 * SA::LD + ks * 16);
+#pragma unroll
+                for (int j = 0; j < RN; ++j)
+#pragma unroll
+                    for (int t = 0; t < 3; ++t)
+                        b[j][t] = *reinterpret_cast<const bf16x8 *>(
+                            Bs + t * SB::PART + j * 32 * SB::LD + ks * 16);
+#pragma unroll
+                for (int i = 0; i < RM; ++i)
+#pragma unroll
+                    for (int j = 0; j < RN; ++j) {
+                        floatx16 &c = acc[i][j];
+                        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][2], c, 0, 0, 0);
+                        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][1], b[j][1], c, 0, 0, 0);
+                        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][2], b[j][0], c, 0, 0, 0);
+                        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][1], c, 0, 0, 0);
+                        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][1], b[j][0], c, 0, 0, 0);
+                        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], b[j][0], c, 0, 0, 0);
+                    }
+            }
+            if (more) {
+                sa.store(nxt, tid);
+                sb.store(nxt + SA::HALVES, tid);
+            }
+            __syncthreads();
+        }
+        wave_sum<KW, RM, RN>(acc, reinterpret_cast<float *>(smem), wave, lane);
+        if (wave == 0) epilogue<RM, RN>(g, acc, m0, n0, lane);
+    }
+};
+
+// ---------------------------------------------------------------------------
 // Tile order: blocks are dispatched round-robin over the 8 XCDs (block b goes
 // to XCD b % 8).  Renumber so that each XCD receives a contiguous range of
 // tile ids, then walk tiles in groups of GROUP_M tile-rows so that the tiles

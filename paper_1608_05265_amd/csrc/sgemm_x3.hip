@@ -22,6 +22,10 @@ using X3P13 = X3PTile<SH, TA, TB, 1, 3>;
 template <class SH, bool TA, bool TB>
 using X3F13 = X3PTile<SH, TA, TB, 1, 3, true>;
 
+// small tiles, four waves splitting each tile's K steps
+template <class SH, bool TA, bool TB>
+using X3W = X3WTile<SH, TA, TB>;
+
 template <template <class, bool, bool> class T, class SH, bool BATCHED, bool SPLITK = false>
 ConfigEntry make_x3(const char *name)
 {
@@ -65,6 +69,8 @@ void register_x3(std::vector<ConfigEntry> &out)
     out.push_back(make_x3<X3S, Shape<128, 128, 32, 64, 64>, true>("x3_128x128x32_w64x64"));
     out.push_back(make_x3<X3D, Shape<128, 128, 32, 64, 64>, true, true>("x3d_128x128x32_w64x64"));
     out.push_back(make_x3<X3S, Shape<64, 64, 32, 32, 32>, true, true>("x3_64x64x32_w32x32"));
+    out.push_back(make_x3<X3W, WShape<64, 64, 64, 4>, true>("x3w_64x64x64_k4"));
+    out.push_back(make_x3<X3W, WShape<32, 32, 64, 4>, true>("x3w_32x32x64_k4"));
 }
 
 }  // namespace misgemm
