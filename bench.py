@@ -261,20 +261,38 @@ def measure_peaks(torch, seconds=2.5, kinds=("fp32", "bf16"), datas=("random", "
 
 
 class Resident:
-    """A problem's operands on the device, C restorable to C0."""
+    """A problem's operands on the device, C restorable to C0.  FP32 calls go
+    through misgemm_sgemm; split-form calls through misgemm_sgemm_ws with a
+    workspace this program owns (allocated before any timing, shared by the
+    problems, which run one after another on one stream), so that the
+    tuning table's packed configurations can serve them."""
+
+    workspace = None
 
     def __init__(self, p, dev):
         import torch
+        import paper_1608_05265_amd as mg
         self.p = p
         self.A = torch.from_numpy(p.A).to(dev)
         self.B = torch.from_numpy(p.B).to(dev)
         self.C0 = torch.from_numpy(p.C0).to(dev)
         self.C = self.C0.clone()
+        need = mg.workspace_size(p.transa, p.transb, p.m, p.n, p.k, mg.BF16X3)
+        ws = Resident.workspace
+        if ws is None or ws.numel() * 4 < need:
+            Resident.workspace = None
+            torch.cuda.empty_cache()
+            Resident.workspace = torch.empty((need + 3) // 4, dtype=torch.float32, device=dev)
 
     def call(self, mg, mode):
         p = self.p
-        mg.sgemm(p.transa, p.transb, p.m, p.n, p.k, p.alpha, self.A, p.lda, self.B, p.ldb,
-                 p.beta, self.C, p.ldc, mode=mode)
+        if mode == mg.BF16X3:
+            ws = Resident.workspace
+            mg.sgemm_ws(p.transa, p.transb, p.m, p.n, p.k, p.alpha, self.A, p.lda, self.B,
+                        p.ldb, p.beta, self.C, p.ldc, mode, ws, ws.numel() * 4)
+        else:
+            mg.sgemm(p.transa, p.transb, p.m, p.n, p.k, p.alpha, self.A, p.lda, self.B, p.ldb,
+                     p.beta, self.C, p.ldc, mode=mode)
 
     def reset(self):
         self.C.copy_(self.C0)
@@ -514,6 +532,8 @@ def batch_line(args, torch, mg):
         del res
         torch.cuda.empty_cache()
     f32 = out["fp32"]
+    algo_bytes = sum(4.0 * (p.m * p.k + p.k * p.n + p.m * p.n * (1 + (p.beta != 0.0)))
+                     for p in problems)
     line = {
         "metric": METRIC,
         "value": round(f32["tflops"], 3),
@@ -528,19 +548,33 @@ def batch_line(args, torch, mg):
         "pct_of_fp32_peak": round(100.0 * f32["tflops"] / PEAK_FP32, 2),
         "bf16x3": {"value": round(out["bf16x3"]["tflops"], 3),
                    "pct_of_bf16_mfma_peak": round(100.0 * 6 * out["bf16x3"]["tflops"] / PEAK_BF16, 2),
-                   "traffic": measured_traffic("batch_bf16x3", BATCH_TRAFFIC_FILE)
-                   if out["bf16x3"]["second_config"] is None else None},
-        "roofline": {"bound": "mfma", "kernel": "persistent batch kernel (%s)" % f32["config"],
+                   "roofline": {
+                       "bound": "mfma",
+                       "kernel": "persistent batch kernel (%s%s)" % (
+                           out["bf16x3"]["config"],
+                           " + " + out["bf16x3"]["second_config"]
+                           if out["bf16x3"]["second_config"] else ""),
+                       "achieved": round(6 * out["bf16x3"]["launch_tflops"], 3),
+                       "peak": PEAK_BF16,
+                       "unit": "TFLOP/s of BF16 MFMA work (6 x the FP32-equivalent rate)",
+                       "frac": round(6 * out["bf16x3"]["launch_tflops"] / PEAK_BF16, 4),
+                       "avg_launch_ms": round(out["bf16x3"]["launch_avg_ms"], 4),
+                       "flops_per_launch": 6 * flops,
+                       "traffic": measured_traffic("batch_bf16x3", BATCH_TRAFFIC_FILE),
+                       "traffic_requests": measured_bytes("batch_bf16x3", BATCH_TRAFFIC_FILE),
+                       "algorithmic_bytes_per_launch": algo_bytes}},
+        "roofline": {"bound": "mfma",
+                     "kernel": "persistent batch kernel (%s%s)" % (
+                         f32["config"], " + " + f32["second_config"] if f32["second_config"]
+                         else ""),
                      "achieved": round(f32["launch_tflops"], 3), "peak": PEAK_FP32,
                      "unit": "TFLOP/s", "frac": round(f32["launch_tflops"] / PEAK_FP32, 4),
                      "avg_launch_ms": round(f32["launch_avg_ms"], 4),
                      "flops_per_launch": flops,
-                     # counters were taken on one-part plans
-                     "traffic": measured_traffic("batch_fp32", BATCH_TRAFFIC_FILE)
-                     if f32["second_config"] is None else None,
-                     "algorithmic_bytes_per_launch": sum(
-                         4.0 * (p.m * p.k + p.k * p.n + p.m * p.n * (1 + (p.beta != 0.0)))
-                         for p in problems)},
+                     # per launch: both parts of a two-part plan
+                     "traffic": measured_traffic("batch_fp32", BATCH_TRAFFIC_FILE),
+                     "traffic_requests": measured_bytes("batch_fp32", BATCH_TRAFFIC_FILE),
+                     "algorithmic_bytes_per_launch": algo_bytes},
         "detail": out,
     }
     if "oracle_seconds" in f32:
@@ -825,6 +859,29 @@ def measured_traffic(form: str, path: str = ""):
     return None
 
 
+def measured_bytes(form: str, path: str = ""):
+    """The L2-to-memory request bytes per launch of a kernel from a committed
+    counter summary (TCC_EA0 read requests by size, 128/64/32 bytes, and
+    write requests, each with the part addressed to the memory controller:
+    Infinity Cache and HBM), or None when the kernel sources, their host
+    scheduling code or the tuning table changed since the counters were
+    taken."""
+    try:
+        with open(path or TRAFFIC_FILE) as f:
+            for line in f:
+                parts = line.split()
+                if len(parts) == 7 and parts[0] == "ea_bytes_per_launch" and parts[1] == form:
+                    if parts[2] != kernel_sources_hash():
+                        return None
+                    rd, rd_dram, wr, wr_dram = (float(v) for v in parts[3:])
+                    return {"read": rd, "read_to_memory": rd_dram, "write": wr,
+                            "write_to_memory": wr_dram, "total": rd + wr,
+                            "unit": "bytes per launch leaving the L2 (TCC_EA0 requests x size)"}
+    except OSError:
+        return None
+    return None
+
+
 def dominant_only(args, torch, mg):
     """The dominant problem alone, for rocprofv3 runs: `steps` calls of the
     8192^3 NN sgemm in each form, then `steps` device-to-device copies of
@@ -1086,7 +1143,9 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": desc, "gemms_per_step": len(res),
-                   "flops_per_step": flops_step, "forms": "fp32 (value), bf16x3 (bf16x3 object)"},
+                   "flops_per_step": flops_step,
+                   "forms": "fp32 (value, misgemm_sgemm), bf16x3 (bf16x3 object, "
+                            "misgemm_sgemm_ws with a caller-owned workspace)"},
         "pct_of_fp32_peak": round(100.0 * f32["tflops"] / PEAK_FP32, 2),
         "bf16x3": {"value": round(x3["tflops"], 3), "unit": "TFLOP/s (FP32-equivalent, 2MNK)",
                    "ms_per_step": round(x3["ms_per_step"], 4),
@@ -1103,8 +1162,11 @@ def main():
             "flops_per_launch": 2.0 * dp.m * dp.n * dp.k,
             "traffic": measured_traffic("fp32") if (dp.m, dp.n, dp.k) == (8192, 8192, 8192)
             else None,
-            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0, "
-                            "copy-kernel calibrated)",
+            "traffic_unit": "bytes per launch beyond the L2, to the memory controller (Infinity "
+                            "Cache and HBM behind it; rocprofv3 FETCH_SIZE and WRITE_SIZE, each "
+                            "scaled by its reading for a copy of known size)",
+            "traffic_requests": measured_bytes("fp32")
+            if (dp.m, dp.n, dp.k) == (8192, 8192, 8192) else None,
             "algorithmic_bytes_per_launch": 4.0 * (dp.m * dp.k + dp.k * dp.n + 2 * dp.m * dp.n),
         },
         "per_problem": per_problem,
@@ -1123,6 +1185,8 @@ def main():
         "flops_per_launch": 6 * 2.0 * dp.m * dp.n * dp.k,
         "traffic": measured_traffic("bf16x3") if (dp.m, dp.n, dp.k) == (8192, 8192, 8192)
         else None,
+        "traffic_requests": measured_bytes("bf16x3")
+        if (dp.m, dp.n, dp.k) == (8192, 8192, 8192) else None,
         "algorithmic_bytes_per_launch": 4.0 * (dp.m * dp.k + dp.k * dp.n + 2 * dp.m * dp.n),
     }
     if not args.no_cpu_baseline:
@@ -1157,7 +1221,7 @@ def main():
         b = batch_line(args, torch, mg)
         line["batch512"] = {"fp32_tflops": b["value"], "bf16x3_tflops": b["bf16x3"]["value"],
                             "roofline": b["roofline"],
-                            "bf16x3_traffic": b["bf16x3"]["traffic"], "detail": b["detail"]}
+                            "bf16x3_roofline": b["bf16x3"]["roofline"], "detail": b["detail"]}
     print(json.dumps(line))
 
 

@@ -77,12 +77,13 @@ typedef enum {
  *   -8 lda, -9 B NULL, -10 ldb, -12 C NULL, -13 ldc, -14 mode.
  * The kernel configuration (tile shape, wave layout, split-K factor) comes
  * from the loaded tuning table when it holds an entry for the shape, else
- * from built-in heuristics.  Two choices use scratch memory that the library
- * owns per (device, stream) -- calls on one stream share it in stream order,
- * calls on different streams never share it: the packed bf16x3
- * configurations (see misgemm_sgemm_ws) and split-K, which the heuristics
- * pick when the C tiles alone would leave CUs idle (each of `splits`
- * workgroups per tile computes a K range and stores its partial tile; a
+ * from built-in heuristics; misgemm_sgemm never picks a packed bf16x3
+ * configuration (those need a workspace: misgemm_sgemm_ws).  One choice uses
+ * scratch memory that the library owns per (device, stream) -- calls on one
+ * stream share it in stream order, calls on different streams never share
+ * it: split-K, which the table or the heuristics pick when the C tiles alone
+ * would leave CUs idle (each of `splits` workgroups per tile computes a K
+ * range and stores its partial tile, splits * tiles * bm * bn * 4 bytes; a
  * second kernel adds the partials in split order and applies alpha/beta, so
  * results are reproducible bit for bit).
  * The scratch is allocated on first need and never while the stream is
@@ -93,7 +94,7 @@ typedef enum {
  * is kept until misgemm_release_workspace().  So a caller that never
  * captures holds one buffer per (device, stream), the size of its largest
  * need.  Callers that must not allocate use misgemm_sgemm_ws (caller-owned
- * workspace) instead.
+ * workspace, no split-K) or misgemm_sgemm_split_noalloc instead.
  */
 int misgemm_sgemm(char transa, char transb, int64_t m, int64_t n, int64_t k,
                   float alpha, const float *A, int64_t lda,
@@ -169,19 +170,22 @@ int misgemm_sgemm_split_noalloc(char transa, char transb, int64_t m, int64_t n, 
  *   of this problem (0 for MISGEMM_FP32); negative = argument error as in
  *   misgemm_sgemm.
  * misgemm_sgemm_ws: misgemm_sgemm with a caller-owned device workspace
- *   (16-byte aligned).  workspace == NULL: a packed configuration is never
- *   chosen and nothing is allocated; otherwise workspace_bytes must cover
- *   misgemm_workspace_size (-16 if not, -15 if misaligned) and the call
- *   allocates nothing (capturable).  The workspace must not be reused by
+ *   (16-byte aligned), in which the tuning table's packed bf16x3
+ *   configurations may run (a table lists, per shape, its fastest entry,
+ *   packed or not, and the fastest non-packed one for misgemm_sgemm).
+ *   workspace == NULL: a packed configuration is never chosen and nothing is
+ *   allocated; otherwise workspace_bytes must cover misgemm_workspace_size
+ *   (-16 if not, -15 if misaligned) and the call allocates nothing
+ *   (capturable).  The workspace must not be reused by
  *   another call before this one completes on `stream`.
  * misgemm_sgemm_ws never uses split-K.
- * misgemm_sgemm itself, in MISGEMM_BF16X3 mode with a packed configuration
- *   selected, uses a workspace the library owns per (device, stream): grown
- *   with hipMalloc when a larger problem arrives (never while the stream is
- *   being captured; then a non-packed configuration is used instead, and
- *   misgemm_sgemm_config with an explicit packed configuration returns
- *   MISGEMM_E_CAPTURING).  Outgrown buffers are freed as described at
- *   misgemm_sgemm, except those that captured graphs may reference.
+ * misgemm_sgemm itself never picks a packed configuration.
+ *   misgemm_sgemm_config with an explicit packed configuration uses the
+ *   scratch the library owns per (device, stream) for the panels: grown with
+ *   hipMalloc when a larger problem arrives (MISGEMM_E_CAPTURING when it
+ *   would have to grow while the stream is being captured); outgrown
+ *   buffers are freed as described at misgemm_sgemm, except those that
+ *   captured graphs may reference.
  * misgemm_release_workspace: synchronizes the current device and frees the
  *   library-owned scratch of that device (all streams); graphs captured
  *   with it must not be replayed afterwards.
@@ -220,7 +224,8 @@ int misgemm_config_info(int id, misgemm_config_desc *out);
 
 /*
  * Which configuration misgemm_sgemm would pick for this problem (tuning
- * table first, then heuristics), or a negative argument error.
+ * table first, then heuristics; never a packed one), or a negative argument
+ * error.
  */
 int misgemm_select_config(char transa, char transb, int64_t m, int64_t n, int64_t k,
                           int mode);
@@ -376,6 +381,11 @@ typedef struct misgemm_batch misgemm_batch; /* opaque plan */
  * <config2>, as two launches that run concurrently (the second on a stream
  * the plan owns, forked from and joined back to the launching stream with
  * events, so misgemm_batch_launch stays capturable).
+ * With a packed bf16x3 configuration the plan also owns panels for every
+ * problem's split operands (6 bytes per element of op(A) and op(B), rows
+ * padded to the tile side), and each launch first packs the operands (one
+ * pack kernel over all problems) and then runs the tile kernel on the
+ * panels; the operands are read at launch time, as for the other plans.
  * On a bad problem returns that problem's argument error (negative, as for
  * misgemm_sgemm) or MISGEMM_E_BATCH and stores its index in *bad_index.
  * Allocates device memory and synchronizes: NOT capturable (returns
@@ -409,6 +419,8 @@ typedef struct {
     double part_imbalance; /* largest list's work / mean list work (>= 1) */
     int second_config_id;  /* -1: one part */
     int64_t second_grid;
+    int64_t panel_bytes;   /* device bytes of split operand panels the plan owns
+                              (packed bf16x3 configurations; 0 otherwise) */
 } misgemm_batch_desc;
 
 int misgemm_batch_info(const misgemm_batch *plan, misgemm_batch_desc *out);

@@ -61,7 +61,7 @@ class BatchDesc(ctypes.Structure):
                 ("config_id", ctypes.c_int), ("flops", ctypes.c_double),
                 ("tile_flops", ctypes.c_double), ("parts", ctypes.c_int),
                 ("part_imbalance", ctypes.c_double), ("second_config_id", ctypes.c_int),
-                ("second_grid", ctypes.c_int64)]
+                ("second_grid", ctypes.c_int64), ("panel_bytes", ctypes.c_int64)]
 
 
 def library_path() -> str:
@@ -377,7 +377,7 @@ class Batch:
         return {"count": d.count, "tiles": d.tiles, "grid": d.grid, "config_id": d.config_id,
                 "flops": d.flops, "tile_flops": d.tile_flops, "parts": d.parts,
                 "part_imbalance": d.part_imbalance, "second_config_id": d.second_config_id,
-                "second_grid": d.second_grid}
+                "second_grid": d.second_grid, "panel_bytes": d.panel_bytes}
 
     def destroy(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value is not None:

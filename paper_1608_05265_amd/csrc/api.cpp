@@ -98,15 +98,19 @@ int find_config(const char *name)
 }
 
 // Nearest tuned entry (same mode and transposes, every size within a factor
-// 2, smallest summed log-distance); -1 when none.
-int tuned_config(int mode, int ta, int tb, int64_t m, int64_t n, int64_t k, int *group_m,
-                 int *splits)
+// 2, smallest summed log-distance; on equal distance the earlier line, so a
+// table lists a key's packed winner before its best non-packed entry), among
+// the non-packed configurations unless allow_packed; -1 when none.
+int tuned_config(int mode, int ta, int tb, int64_t m, int64_t n, int64_t k, bool allow_packed,
+                 int *group_m, int *splits)
 {
+    const auto &table = configs();
     std::lock_guard<std::mutex> lock(g_tune_mutex);
     int best = -1;
     double best_d = 1e300;
     for (const TuneEntry &e : g_tuning) {
         if (e.mode != mode || e.ta != ta || e.tb != tb) continue;
+        if (!allow_packed && table[e.config].desc.packed) continue;
         const double dm = fabs(log2((double)m / (double)e.m));
         const double dn = fabs(log2((double)n / (double)e.n));
         const double dk = fabs(log2((double)k / (double)e.k));
@@ -150,8 +154,8 @@ int select_config(int mode, int ta, int tb, int64_t m, int64_t n, int64_t k, int
 {
     *group_m = GROUP_M_DEFAULT;
     *splits = 0;
-    const int c = tuned_config(mode, ta, tb, m, n, k, group_m, splits);
-    if (c >= 0 && (allow_packed || !configs()[c].desc.packed)) return c;
+    const int c = tuned_config(mode, ta, tb, m, n, k, allow_packed, group_m, splits);
+    if (c >= 0) return c;
     *group_m = GROUP_M_DEFAULT;
     *splits = 0;
     return heuristic_config(mode, m, n, k, cus, allow_packed);
@@ -378,7 +382,10 @@ int run_sgemm(char transa, char transb, int64_t m, int64_t n, int64_t k, float a
     if (alpha == 0.0f || k == 0) return (int)launch_scale(beta, C, m, n, ldc, s);
     const int ta = trans_flag(transa), tb = trans_flag(transb);
     int gm = group_m > 0 ? group_m : GROUP_M_DEFAULT;
-    const bool packable = mode == MISGEMM_BF16X3 && policy != WS_NONE && policy != WS_STATIC &&
+    // A packed configuration is chosen only when the caller passed its
+    // workspace (misgemm_sgemm_ws): misgemm_sgemm allocates nothing for it.
+    // One requested explicitly (misgemm_sgemm_config) uses the library scratch.
+    const bool packable = mode == MISGEMM_BF16X3 && policy == WS_CALLER &&
                           pack_kblocks(k) <= 65535;
     int cfg = config_id;
     int splits = splits_req;
@@ -451,6 +458,15 @@ struct misgemm_batch {
     ProbDev *d_probs;
     TileDev *d_tiles;
     int device;
+    // packed configurations: every operand split once into panels the plan
+    // owns (one pack launch), then the tile kernel on the panels
+    bool packed;
+    PackedArgs *d_pprobs;
+    PackJob *d_jobs;
+    int njobs;
+    int64_t pack_blocks;
+    void *d_panels;
+    int64_t panel_bytes;
     // two-part plans: the problems below the size threshold in their own
     // plan, launched on `side` between the fork and join events
     misgemm_batch *second;
@@ -472,6 +488,15 @@ int build_part(const misgemm_problem *problems, const std::vector<int64_t> &inde
     std::vector<int64_t> first;  // per problem: index of its first tile
     probs.reserve(index.size());
     double flops = 0.0, tile_flops = 0.0;
+    // packed: panel rows padded to the larger tile side (so every tile reads
+    // inside its panels), panels 256-byte aligned in one plan-owned buffer
+    const bool packed = d.packed != 0;
+    const int64_t pad_rows = std::max(d.bm, d.bn);
+    std::vector<PackedArgs> pprobs;
+    std::vector<PackJob> jobs;
+    std::vector<int64_t> a_off, b_off;  // panel offsets, in bf16 elements
+    int64_t panel_halves = 0, pack_blocks = 0;
+    auto round_up = [](int64_t x, int64_t q) { return (x + q - 1) / q * q; };
     for (const int64_t i : index) {
         const misgemm_problem &p = problems[i];
         if (p.m == 0 || p.n == 0) continue;
@@ -490,6 +515,30 @@ int build_part(const misgemm_problem *problems, const std::vector<int64_t> &inde
         }
         const int32_t idx = (int32_t)probs.size();
         probs.push_back(pd);
+        if (packed) {
+            PackedArgs pa;
+            pa.g = pd.g;
+            pa.mp = round_up(p.m, pad_rows);
+            pa.np = round_up(p.n, pad_rows);
+            pa.kblocks = pack_kblocks(pd.g.k);
+            pa.Ap = pa.Bp = nullptr;  // set once the panel buffer exists
+            a_off.push_back(panel_halves);
+            panel_halves += round_up(pa.kblocks * 3 * pa.mp * PACK_K, 128);
+            b_off.push_back(panel_halves);
+            panel_halves += round_up(pa.kblocks * 3 * pa.np * PACK_K, 128);
+            if (pa.kblocks > 0) {
+                // op(A) is k-contiguous when A is transposed, op(B) when B is not
+                const PackJob ja = {p.A, nullptr, p.lda, p.m, pd.g.k, pa.mp, pack_blocks,
+                                    (pa.mp + 255) / 256, pd.ta != 0, pd.g.vec_a};
+                pack_blocks += ja.row_blocks * pa.kblocks;
+                const PackJob jb = {p.B, nullptr, p.ldb, p.n, pd.g.k, pa.np, pack_blocks,
+                                    (pa.np + 255) / 256, pd.tb == 0, pd.g.vec_b};
+                pack_blocks += jb.row_blocks * pa.kblocks;
+                jobs.push_back(ja);
+                jobs.push_back(jb);
+            }
+            pprobs.push_back(pa);
+        }
         first.push_back((int64_t)tiles.size());
         flops += 2.0 * (double)p.m * (double)p.n * (double)pd.g.k;
         tile_flops += 2.0 * (double)(pd.tiles_m * d.bm) * (double)(pd.tiles_n * d.bn) *
@@ -570,20 +619,55 @@ int build_part(const misgemm_problem *problems, const std::vector<int64_t> &inde
     b->part_imbalance = total_work > 0 ? (double)max_load * nx / (double)total_work : 1.0;
     (void)hipGetDevice(&b->device);
     b->grid = (int)grid;
+    b->packed = packed;
+    if (packed && (pack_blocks > INT32_MAX || jobs.size() > (size_t)INT32_MAX)) {
+        free(b);
+        return MISGEMM_E_TOO_LARGE;
+    }
     hipError_t e = hipSuccess;
     if (!probs.empty()) {
-        e = hipMalloc((void **)&b->d_probs, probs.size() * sizeof(ProbDev));
-        if (e == hipSuccess) e = hipMalloc((void **)&b->d_tiles, sorted.size() * sizeof(TileDev));
-        if (e == hipSuccess)
-            e = hipMemcpy(b->d_probs, probs.data(), probs.size() * sizeof(ProbDev),
-                          hipMemcpyHostToDevice);
+        e = hipMalloc((void **)&b->d_tiles, sorted.size() * sizeof(TileDev));
         if (e == hipSuccess)
             e = hipMemcpy(b->d_tiles, sorted.data(), sorted.size() * sizeof(TileDev),
                           hipMemcpyHostToDevice);
+        if (!packed) {
+            if (e == hipSuccess) e = hipMalloc((void **)&b->d_probs, probs.size() * sizeof(ProbDev));
+            if (e == hipSuccess)
+                e = hipMemcpy(b->d_probs, probs.data(), probs.size() * sizeof(ProbDev),
+                              hipMemcpyHostToDevice);
+        } else {
+            b->panel_bytes = panel_halves * 2;
+            if (e == hipSuccess && b->panel_bytes > 0) e = hipMalloc(&b->d_panels, (size_t)b->panel_bytes);
+            __bf16 *base = reinterpret_cast<__bf16 *>(b->d_panels);
+            size_t jn = 0;
+            for (size_t i = 0; i < pprobs.size(); ++i) {
+                pprobs[i].Ap = base + a_off[i];
+                pprobs[i].Bp = base + b_off[i];
+                if (pprobs[i].kblocks > 0) {
+                    jobs[jn++].out = base + a_off[i];
+                    jobs[jn++].out = base + b_off[i];
+                }
+            }
+            b->njobs = (int)jobs.size();
+            b->pack_blocks = pack_blocks;
+            if (e == hipSuccess)
+                e = hipMalloc((void **)&b->d_pprobs, pprobs.size() * sizeof(PackedArgs));
+            if (e == hipSuccess)
+                e = hipMemcpy(b->d_pprobs, pprobs.data(), pprobs.size() * sizeof(PackedArgs),
+                              hipMemcpyHostToDevice);
+            if (e == hipSuccess && !jobs.empty())
+                e = hipMalloc((void **)&b->d_jobs, jobs.size() * sizeof(PackJob));
+            if (e == hipSuccess && !jobs.empty())
+                e = hipMemcpy(b->d_jobs, jobs.data(), jobs.size() * sizeof(PackJob),
+                              hipMemcpyHostToDevice);
+        }
     }
     if (e != hipSuccess) {
         if (b->d_probs) (void)hipFree(b->d_probs);
         if (b->d_tiles) (void)hipFree(b->d_tiles);
+        if (b->d_pprobs) (void)hipFree(b->d_pprobs);
+        if (b->d_jobs) (void)hipFree(b->d_jobs);
+        if (b->d_panels) (void)hipFree(b->d_panels);
         free(b);
         return (int)e;
     }
@@ -799,7 +883,7 @@ int misgemm_select_config(char transa, char transb, int64_t m, int64_t n, int64_
     int cus = 256;
     if (current_device(&dev) == 0) cus = dev->cus;
     int gm = 0, splits = 0;
-    return select_config(mode, ta, tb, m, n, k, cus, mode == MISGEMM_BF16X3, &gm, &splits);
+    return select_config(mode, ta, tb, m, n, k, cus, false, &gm, &splits);
 }
 
 int misgemm_load_tuning(const char *path)
@@ -832,8 +916,8 @@ int misgemm_load_tuning(const char *path)
                 }
                 const int b = find_config(name), sm = find_config(name2);
                 if (b < 0 || sm < 0 || configs()[b].desc.mode != mode ||
-                    configs()[sm].desc.mode != mode || !configs()[b].batch ||
-                    !configs()[sm].batch) {
+                    configs()[sm].desc.mode != mode || !has_batch(configs()[b]) ||
+                    !has_batch(configs()[sm])) {
                     rc = MISGEMM_E_TUNING_FILE;
                     break;
                 }
@@ -846,7 +930,7 @@ int misgemm_load_tuning(const char *path)
                     break;
                 }
                 const int id = find_config(name);
-                if (id < 0 || configs()[id].desc.mode != mode || !configs()[id].batch) {
+                if (id < 0 || configs()[id].desc.mode != mode || !has_batch(configs()[id])) {
                     rc = MISGEMM_E_TUNING_FILE;
                     break;
                 }
@@ -904,7 +988,7 @@ int misgemm_batch_plan(const misgemm_problem *problems, int64_t count, int mode,
     // problem carrying the most work, among configs with a batched variant
     int cfg = config_id;
     if (cfg >= 0) {
-        if (cfg >= (int)table.size() || table[cfg].desc.mode != mode || !table[cfg].batch)
+        if (cfg >= (int)table.size() || table[cfg].desc.mode != mode || !has_batch(table[cfg]))
             return MISGEMM_E_BAD_CONFIG;
     } else {
         {
@@ -914,7 +998,7 @@ int misgemm_batch_plan(const misgemm_problem *problems, int64_t count, int mode,
         int64_t smallest = INT64_MAX;
         for (size_t i = 0; i < table.size(); ++i) {
             const misgemm_config_desc &d = table[i].desc;
-            if (d.mode != mode || !table[i].batch) continue;
+            if (d.mode != mode || !has_batch(table[i])) continue;
             // default: the 128x128 tile if compiled, else the smallest
             const int64_t area = (int64_t)d.bm * d.bn;
             if (d.bm == 128 && d.bn == 128 && cfg < 0) cfg = (int)i;
@@ -922,7 +1006,7 @@ int misgemm_batch_plan(const misgemm_problem *problems, int64_t count, int mode,
         }
         if (cfg < 0)
             for (size_t i = 0; i < table.size(); ++i)
-                if (table[i].desc.mode == mode && table[i].batch &&
+                if (table[i].desc.mode == mode && has_batch(table[i]) &&
                     (int64_t)table[i].desc.bm * table[i].desc.bn == smallest) { cfg = (int)i; break; }
         if (cfg < 0) return MISGEMM_E_BAD_CONFIG;
     }
@@ -981,6 +1065,11 @@ int misgemm_batch_launch(const misgemm_batch *plan, void *stream)
     auto run = [](const misgemm_batch *p, hipStream_t st) -> int {
         if (p->ntiles == 0) return 0;
         const ConfigEntry &c = configs()[p->config_id];
+        if (p->packed) {
+            const hipError_t e = launch_pack_batch(p->d_jobs, p->njobs, p->pack_blocks, st);
+            if (e != hipSuccess) return (int)e;
+            return (int)c.packed_batch(p->d_pprobs, p->d_tiles, p->split, p->grid, st);
+        }
         return (int)c.batch(p->d_probs, p->d_tiles, p->split, p->grid, st);
     };
     if (plan->second == nullptr) return run(plan, s);
@@ -1012,6 +1101,7 @@ int misgemm_batch_info(const misgemm_batch *plan, misgemm_batch_desc *out)
     out->part_imbalance = plan->part_imbalance;
     out->second_config_id = q ? q->config_id : -1;
     out->second_grid = q ? q->grid : 0;
+    out->panel_bytes = plan->panel_bytes + (q ? q->panel_bytes : 0);
     return 0;
 }
 
@@ -1025,6 +1115,9 @@ int misgemm_batch_destroy(misgemm_batch *plan)
     if (plan->side) (void)hipStreamDestroy(plan->side);
     if (plan->d_probs) (void)hipFree(plan->d_probs);
     if (plan->d_tiles) (void)hipFree(plan->d_tiles);
+    if (plan->d_pprobs) (void)hipFree(plan->d_pprobs);
+    if (plan->d_jobs) (void)hipFree(plan->d_jobs);
+    if (plan->d_panels) (void)hipFree(plan->d_panels);
     free(plan);
     return (int)e;
 }

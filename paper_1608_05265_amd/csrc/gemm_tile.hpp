@@ -351,7 +351,7 @@ __device__ __forceinline__ void finish(const GemmArgs &g, const floatx16 (&acc)[
 // ---------------------------------------------------------------------------
 // The tile body: stage -> multiply -> epilogue for tile (m0, n0).
 // ---------------------------------------------------------------------------
-template <class SH, bool TA, bool TB>
+template <class SH, bool TA, bool TB, bool PF2 = false>
 struct F32Tile {
     using SA = StageF32<SH::BM, SH::BK, SH::NT, TA>;   // A is K-contiguous when transposed
     using SB = StageF32<SH::BN, SH::BK, SH::NT, !TB>;  // B is K-contiguous when not transposed
@@ -391,18 +391,33 @@ struct F32Tile {
         const int64_t ktiles = (g.k + SH::BK - 1) / SH::BK;
         SA sa;
         SB sb;
+        // PF2: a second register set takes the global loads of block kt+2
+        // at the top of block kt and moves into the first set at its end, so
+        // a load has two blocks of MFMA time to arrive instead of one
+        SA sa2;
+        SB sb2;
         if (ktiles > 0) {
             sa.template load<FAST>(g.A, g.lda, m0, 0, g.m, g.k, g.vec_a, tid);
             sb.template load<FAST>(g.B, g.ldb, n0, 0, g.n, g.k, g.vec_b, tid);
             sa.store(lds, tid);
             sb.store(lds + SA::FLOATS, tid);
         }
+        if (PF2 && ktiles > 1) {
+            sa.template load<FAST>(g.A, g.lda, m0, SH::BK, g.m, g.k, g.vec_a, tid);
+            sb.template load<FAST>(g.B, g.ldb, n0, SH::BK, g.n, g.k, g.vec_b, tid);
+        }
         __syncthreads();
         for (int64_t kt = 0; kt < ktiles; ++kt) {
             float *cur = lds + (kt & 1) * STAGE_FLOATS;
             float *nxt = lds + ((kt + 1) & 1) * STAGE_FLOATS;
             const bool more = kt + 1 < ktiles;
-            if (more) {
+            if (PF2) {
+                if (kt + 2 < ktiles) {
+                    const int64_t k0 = (kt + 2) * SH::BK;
+                    sa2.template load<FAST>(g.A, g.lda, m0, k0, g.m, g.k, g.vec_a, tid);
+                    sb2.template load<FAST>(g.B, g.ldb, n0, k0, g.n, g.k, g.vec_b, tid);
+                }
+            } else if (more) {
                 const int64_t k0 = (kt + 1) * SH::BK;
                 sa.template load<FAST>(g.A, g.lda, m0, k0, g.m, g.k, g.vec_a, tid);
                 sb.template load<FAST>(g.B, g.ldb, n0, k0, g.n, g.k, g.vec_b, tid);
@@ -427,6 +442,10 @@ struct F32Tile {
             if (more) {
                 sa.store(nxt, tid);
                 sb.store(nxt + SA::FLOATS, tid);
+            }
+            if (PF2 && kt + 2 < ktiles) {
+                sa = sa2;
+                sb = sb2;
             }
             __syncthreads();
         }
@@ -670,7 +689,8 @@ struct X3Tile {
 // split and LDS store of block kt+1 are interleaved between the remaining
 // ones.  One workgroup barrier per K block.
 // ---------------------------------------------------------------------------
-template <class SH, bool TA, bool TB, int Q0_NUM = 1, int Q0_DEN = 3, bool FENCED = false>
+template <class SH, bool TA, bool TB, int Q0_NUM = 1, int Q0_DEN = 3, bool FENCED = false,
+          bool PF2 = false>
 struct X3PTile {
     using SA = StageX3<SH::BM, SH::BK, SH::NT, TA>;
     using SB = StageX3<SH::BN, SH::BK, SH::NT, !TB>;
@@ -846,6 +866,47 @@ struct X3PTile {
                 for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
 
         const int64_t ktiles = (g.k + SH::BK - 1) / SH::BK;
+        if constexpr (PF2) {
+            // Two register sets: the global loads of block kt+2 go to the
+            // second set at the top of block kt, while the first set (block
+            // kt+1, loaded a whole block earlier) is split and stored between
+            // the MFMAs; at the end of the block the second set moves into
+            // the first.  A load thus has a block and a third of MFMA time to
+            // arrive instead of a third, and the one body keeps the
+            // accumulators in place.
+            SA sa, sa2;
+            SB sb, sb2;
+            if (ktiles > 0) {
+                sa.template load<FAST>(g.A, g.lda, m0, 0, g.m, g.k, g.vec_a, tid);
+                sb.template load<FAST>(g.B, g.ldb, n0, 0, g.n, g.k, g.vec_b, tid);
+                sa.store(lds, tid);
+                sb.store(lds + SA::HALVES, tid);
+            }
+            if (ktiles > 1) {
+                sa.template load<FAST>(g.A, g.lda, m0, SH::BK, g.m, g.k, g.vec_a, tid);
+                sb.template load<FAST>(g.B, g.ldb, n0, SH::BK, g.n, g.k, g.vec_b, tid);
+            }
+            __syncthreads();
+            for (int64_t kt = 0; kt < ktiles; ++kt) {
+                const __bf16 *cur = lds + (kt & 1) * STAGE_HALVES;
+                __bf16 *nxt = lds + ((kt + 1) & 1) * STAGE_HALVES;
+                if (kt + 2 < ktiles) {
+                    const int64_t k0 = (kt + 2) * SH::BK;
+                    sa2.template load<FAST>(g.A, g.lda, m0, k0, g.m, g.k, g.vec_a, tid);
+                    sb2.template load<FAST>(g.B, g.ldb, n0, k0, g.n, g.k, g.vec_b, tid);
+                }
+                // a store whose block does not exist rewrites an idle stage
+                // that nothing reads again
+                body<true>(acc, cur, nxt, sa, sb, tid, wm, wn, half, l32);
+                if (kt + 2 < ktiles) {
+                    sa = sa2;
+                    sb = sb2;
+                }
+                __syncthreads();
+            }
+            finish<SPLIT, RM, RN>(g, acc, m0 + wm * SH::WM, n0 + wn * SH::WN, tid, NT);
+            return;
+        }
         SA sa;
         SB sb;
         if (ktiles > 0) {

@@ -34,17 +34,16 @@ __host__ __device__ inline int64_t pack_halves(int64_t rows, int64_t k)
     return pack_kblocks(k) * 3 * pack_rows_pad(rows) * PACK_K;
 }
 
-// One thread per (row, 16-k block).  KC: op(X)(r, k) = X[k + r*ld] (k
-// contiguous); otherwise X[r + k*ld] (rows contiguous, so a wave's loads of
-// one k are coalesced).
+// One thread per (row, 16-k block): row r, k block kb of op(X), split and
+// written to the three part runs of its panel.  KC: op(X)(r, k) = X[k + r*ld]
+// (k contiguous); otherwise X[r + k*ld] (rows contiguous, so a wave's loads
+// of one k are coalesced).  Rows in [rows, rows_pad) and k past kdim are
+// written as zeros.
 template <bool KC>
-__global__ __launch_bounds__(256) void pack_x3_kernel(const float *__restrict__ X, int64_t ld,
-                                                      int64_t rows, int64_t kdim,
-                                                      int64_t rows_pad, int vec,
-                                                      __bf16 *__restrict__ out)
+__device__ __forceinline__ void pack_unit(const float *__restrict__ X, int64_t ld, int64_t rows,
+                                          int64_t kdim, int64_t rows_pad, int vec,
+                                          __bf16 *__restrict__ out, int64_t r, int64_t kb)
 {
-    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t kb = blockIdx.y;
     const int64_t k0 = kb * PACK_K;
     float v[PACK_K];
     const bool in_r = r < rows;
@@ -82,6 +81,27 @@ __global__ __launch_bounds__(256) void pack_x3_kernel(const float *__restrict__ 
         *reinterpret_cast<bf16x8 *>(dst + 8) = hi[t];
     }
 }
+
+template <bool KC>
+__global__ __launch_bounds__(256) void pack_x3_kernel(const float *__restrict__ X, int64_t ld,
+                                                      int64_t rows, int64_t kdim,
+                                                      int64_t rows_pad, int vec,
+                                                      __bf16 *__restrict__ out)
+{
+    pack_unit<KC>(X, ld, rows, kdim, rows_pad, vec, out, (int64_t)blockIdx.x * 256 + threadIdx.x,
+                  blockIdx.y);
+}
+
+// One operand of one problem of a packed batch: its blocks of 256 rows x 16
+// k are blocks [first_block, first_block + row_blocks * kblocks) of the
+// batch's pack launch (row block fastest).
+struct PackJob {
+    const float *X;
+    __bf16 *out;
+    int64_t ld, rows, kdim, rows_pad;
+    int64_t first_block, row_blocks;
+    int32_t kc, vec;
+};
 
 // Arguments of the packed tile kernel.
 struct PackedArgs {

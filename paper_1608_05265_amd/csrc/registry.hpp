@@ -42,6 +42,10 @@ typedef hipError_t (*batch_launch_fn)(const ProbDev *probs, const TileDev *tiles
                                       const BatchSplit &split, int grid, hipStream_t s);
 typedef int (*occupancy_fn)();
 typedef hipError_t (*packed_launch_fn)(const PackedArgs &p, int group_m, hipStream_t s);
+// Persistent kernel over the tiles of a batch whose operands were packed
+// (one PackedArgs per problem).
+typedef hipError_t (*packed_batch_fn)(const PackedArgs *probs, const TileDev *tiles,
+                                      const BatchSplit &split, int grid, hipStream_t s);
 
 struct ConfigEntry {
     misgemm_config_desc desc;
@@ -50,7 +54,11 @@ struct ConfigEntry {
     batch_launch_fn batch;     // NULL when no persistent variant is compiled
     occupancy_fn batch_occupancy;
     packed_launch_fn packed;   // tile kernel on packed panels (packed configs only)
+    packed_batch_fn packed_batch;  // persistent variant of it (NULL when not compiled)
 };
+
+// A batched (persistent) variant of either kind is compiled.
+inline bool has_batch(const ConfigEntry &e) { return e.batch != nullptr || e.packed_batch != nullptr; }
 
 // Default number of tile-rows walked together (see tile_coords).
 constexpr int GROUP_M_DEFAULT = 8;
@@ -216,6 +224,9 @@ void register_x3k(std::vector<ConfigEntry> &out);
 // Pack op(X) (rows x k, KC: k contiguous) into split panels (packed_x3.hpp).
 hipError_t launch_pack(const float *X, int64_t ld, bool kc, int64_t rows, int64_t k, int vec,
                        __bf16 *out, hipStream_t s);
+// Pack every operand of a batch in one launch: jobs sorted by first_block,
+// `blocks` = the blocks of all jobs.
+hipError_t launch_pack_batch(const PackJob *jobs, int njobs, int64_t blocks, hipStream_t s);
 
 // Host helpers shared by the entry points.
 hipError_t launch_scale(float beta, float *C, int64_t m, int64_t n, int64_t ldc, hipStream_t s);

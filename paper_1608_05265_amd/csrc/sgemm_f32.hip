@@ -13,6 +13,9 @@ template <class SH, bool TA, bool TB>
 using F32P = F32PTile<SH, TA, TB>;
 template <class SH, bool TA, bool TB>
 using F32W = F32WTile<SH, TA, TB>;
+// global loads two K blocks ahead (two register sets)
+template <class SH, bool TA, bool TB>
+using F32Q = F32Tile<SH, TA, TB, true>;
 
 template <template <class, bool, bool> class T, class SH, bool BATCHED, bool SPLITK = false>
 ConfigEntry make_f32(const char *name)
@@ -58,6 +61,9 @@ void register_f32(std::vector<ConfigEntry> &out)
     out.push_back(make_f32<F32, Shape<128, 128, 16, 64, 64>, true, true>("fp32_128x128x16_w64x64"));
     out.push_back(make_f32<F32, Shape<128, 64, 16, 64, 32>, true>("fp32_128x64x16_w64x32"));
     out.push_back(make_f32<F32, Shape<64, 64, 16, 32, 32>, true, true>("fp32_64x64x16_w32x32"));
+    out.push_back(make_f32<F32Q, Shape<64, 64, 16, 32, 32>, true, true>("fp32q_64x64x16_w32x32"));
+    out.push_back(make_f32<F32Q, Shape<128, 128, 16, 64, 64>, true, true>("fp32q_128x128x16_w64x64"));
+    out.push_back(make_f32<F32Q, Shape<128, 64, 16, 64, 32>, true>("fp32q_128x64x16_w64x32"));
     // small tiles, four waves splitting each tile's K steps
     out.push_back(make_f32<F32W, WShape<64, 64, 32, 4>, true>("fp32w_64x64x32_k4"));
     out.push_back(make_f32<F32W, WShape<32, 32, 32, 4>, true>("fp32w_32x32x32_k4"));

@@ -21,6 +21,9 @@ using X3P13 = X3PTile<SH, TA, TB, 1, 3>;
 // the same with the order pinned by fences instead of group barriers
 template <class SH, bool TA, bool TB>
 using X3F13 = X3PTile<SH, TA, TB, 1, 3, true>;
+// pipelined with the global loads two K blocks ahead (two register sets)
+template <class SH, bool TA, bool TB>
+using X3Q13 = X3PTile<SH, TA, TB, 1, 3, false, true>;
 
 // small tiles, four waves splitting each tile's K steps
 template <class SH, bool TA, bool TB>
@@ -66,6 +69,7 @@ void register_x3(std::vector<ConfigEntry> &out)
     out.push_back(make_x3<X3F13, Shape<256, 256, 16, 64, 128>, false>("x3f_256x256x16_w64x128"));
     out.push_back(make_x3<X3F13, Shape<256, 256, 16, 128, 128>, false>("x3f_256x256x16_w128x128"));
     out.push_back(make_x3<X3P13, Shape<128, 128, 16, 64, 64>, true, true>("x3p_128x128x16_w64x64"));
+    out.push_back(make_x3<X3Q13, Shape<128, 128, 16, 64, 64>, true, true>("x3q_128x128x16_w64x64"));
     out.push_back(make_x3<X3S, Shape<128, 128, 32, 64, 64>, true>("x3_128x128x32_w64x64"));
     out.push_back(make_x3<X3D, Shape<128, 128, 32, 64, 64>, true, true>("x3d_128x128x32_w64x64"));
     out.push_back(make_x3<X3S, Shape<64, 64, 32, 32, 32>, true, true>("x3_64x64x32_w32x32"));

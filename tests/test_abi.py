@@ -126,7 +126,8 @@ def test_quick_returns_need_no_device(mg):
 def test_tuning_table_parsing(mg, tmp_path):
     cfgs = mg.configs()
     f32 = [c for c in cfgs if c["mode"] == 0]
-    x3 = [c for c in cfgs if c["mode"] == 1]
+    x3 = [c for c in cfgs if c["mode"] == 1 and not c["packed"]]
+    x3p = [c for c in cfgs if c["mode"] == 1 and c["packed"]]
     good = tmp_path / "good.txt"
     good.write_text("misgemm-tuning 1\n# comment\n0 N T 4096 4096 4096 %s 4\n"
                     "1 T N 1000 2000 300 %s\n" % (f32[-1]["name"], x3[-1]["name"]))
@@ -148,6 +149,14 @@ def test_tuning_table_parsing(mg, tmp_path):
     mg.load_tuning(str(rule))
     mg.load_tuning(str(good))
     assert mg.select_config("t", "n", 1000, 2000, 300, 1) == x3[-1]["id"]
+    # a packed winner listed first is passed over by misgemm_sgemm's choice,
+    # which takes the key's non-packed entry
+    both = tmp_path / "both.txt"
+    both.write_text("misgemm-tuning 1\n1 T N 1000 2000 300 %s\n1 T N 1000 2000 300 %s\n"
+                    % (x3p[0]["name"], x3[0]["name"]))
+    mg.load_tuning(str(both))
+    assert mg.select_config("T", "N", 1000, 2000, 300, 1) == x3[0]["id"]
+    mg.load_tuning(str(good))
     bad_cases = ["nonsense\n", "misgemm-tuning 1\n0 N N 1 1 1 no_such_config\n",
                  "misgemm-tuning 1\n1 N N 64 64 64 %s\n" % f32[0]["name"],  # mode mismatch
                  "misgemm-tuning 1\n0 Q N 64 64 64 %s\n" % f32[0]["name"],

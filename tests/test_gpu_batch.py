@@ -206,3 +206,56 @@ def test_batch_two_part_rule(mode, tmp_path):
         plan.destroy()
     finally:
         mg.load_tuning(mg.TUNING_PATH)
+
+
+def test_packed_batch_matches_single_packed_calls_and_replays():
+    """A packed split-form plan (operands split once into plan-owned panels,
+    then the persistent tile kernel on them) gives the same bits as the
+    same packed configuration called problem by problem, and its graph
+    replays (pack launch + tile launch) repeat them after the operands
+    change and change back."""
+    import torch
+    import paper_1608_05265_amd as mg
+    problems = wl.config5(count=40, seed_case=8, lo=1, hi=20, step=11)
+    problems.append(wl.make_problem("T", "T", 77, 130, 45, 1.5, -0.5, 15, pad=2))
+    for cfg in [c for c in mg.configs(1) if c["packed"]]:
+        dev, c0, descs = _setup(problems)
+        try:
+            plan = mg.Batch(descs, mode=1, config_id=cfg["id"])
+        except mg.MisgemmError as e:
+            assert e.status == 1001  # no persistent variant
+            continue
+        info = plan.info()
+        assert info["panel_bytes"] > 0
+        plan.launch()
+        torch.cuda.synchronize()
+        got = [C.clone() for (_, _, C) in dev]
+        _check_all(problems, dev, True, cfg["name"])
+        for p, (A, B, C), c, ref in zip(problems, dev, c0, got):
+            C.copy_(c)
+            mg.sgemm_config(p.transa, p.transb, p.m, p.n, p.k, p.alpha, A, p.lda, B, p.ldb,
+                            p.beta, C, p.ldc, 1, cfg["id"])
+            torch.cuda.synchronize()
+            assert torch.equal(C.view(torch.int32), ref.view(torch.int32)), (cfg["name"], p.label)
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.graph(g, stream=side):
+            plan.launch(side)
+        A0 = dev[0][0]
+        saved = A0.clone()
+        for rep in range(3):
+            for (_, _, C), c in zip(dev, c0):
+                C.copy_(c)
+            A0.mul_(2.0 if rep == 1 else 1.0)   # the pack reads the operands at replay
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            for i, ((_, _, C), ref) in enumerate(zip(dev, got)):
+                if rep == 1 and i == 0:
+                    assert not torch.equal(C.view(torch.int32), ref.view(torch.int32))
+                else:
+                    assert torch.equal(C.view(torch.int32), ref.view(torch.int32)), (rep, i)
+            A0.copy_(saved)
+        del g
+        plan.destroy()

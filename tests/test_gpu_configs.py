@@ -276,7 +276,8 @@ def test_non_default_stream():
 
 def test_concurrent_host_threads_on_own_streams():
     """Four host threads, each on its own stream with its own C, run the
-    packed bf16x3 path (4096^3 NT, library scratch per stream) and split-K
+    packed bf16x3 path (4096^3 NT through an explicit packed configuration,
+    library scratch per stream) and split-K
     (128x512x8192, partial tiles in that scratch) at the same time, five
     rounds each: every result equals, bit for bit, the same call made alone
     on the default stream (the split-K ones are also checked against the
@@ -288,12 +289,23 @@ def test_concurrent_host_threads_on_own_streams():
     skinny = wl.make_problem("N", "N", 128, 512, 8192, 1.5, -0.5, 8401)
     jobs = [(big, 1), (big, 1), (skinny, 0), (skinny, 1)]
     dev = {id(p): gu.dev_problem(p) for p in (big, skinny)}
+    packed_id = [c["id"] for c in mg.configs(1) if c["packed"]][0]
+
+    def call(p, mode, A, B, C, stream=None):
+        # the big problem through an explicit packed configuration (library
+        # panels per stream), the skinny one through the default dispatch
+        # (split-K, library partial tiles per stream)
+        if p is big:
+            mg.sgemm_config(p.transa, p.transb, p.m, p.n, p.k, p.alpha, A, p.lda, B, p.ldb,
+                            p.beta, C, p.ldc, mode, packed_id, stream=stream)
+        else:
+            mg.sgemm(p.transa, p.transb, p.m, p.n, p.k, p.alpha, A, p.lda, B, p.ldb, p.beta, C,
+                     p.ldc, mode=mode, stream=stream)
     refs = []
     for p, mode in jobs:
         A, B, _ = dev[id(p)]
         C = torch.from_numpy(p.C0.copy()).to(A.device)
-        mg.sgemm(p.transa, p.transb, p.m, p.n, p.k, p.alpha, A, p.lda, B, p.ldb, p.beta, C,
-                 p.ldc, mode=mode)
+        call(p, mode, A, B, C)
         torch.cuda.synchronize()
         refs.append(C.cpu().numpy().view(np.uint32).copy())
     for (p, mode), ref in zip(jobs[2:], refs[2:]):
@@ -310,8 +322,7 @@ def test_concurrent_host_threads_on_own_streams():
                 C = torch.empty_like(C0)
                 for _ in range(5):
                     C.copy_(C0)
-                    mg.sgemm(p.transa, p.transb, p.m, p.n, p.k, p.alpha, A, p.lda, B, p.ldb,
-                             p.beta, C, p.ldc, mode=mode, stream=s)
+                    call(p, mode, A, B, C, stream=s)
                     s.synchronize()
                     got = C.cpu().numpy().view(np.uint32)
                     if not np.array_equal(got, refs[i]):
@@ -343,9 +354,9 @@ def test_packed_path_caller_workspace_and_capture():
     ws = torch.empty((need + 3) // 4, dtype=torch.float32, device="cuda")
     ref = gu.run(p, 1, config_id=packed[0]["id"], tensors=(A, B, C)).copy()
     gu.check_full(p, ref, "packed via library workspace")
-    mg.load_tuning(None)  # heuristics: a packed config for this bf16x3 shape
+    mg.load_tuning(None)  # heuristics: a packed config only with a workspace
     try:
-        assert mg.config_info(mg.select_config("T", "N", 4096, 4096, 4096, 1))["packed"] == 1
+        assert mg.config_info(mg.select_config("T", "N", 4096, 4096, 4096, 1))["packed"] == 0
         C.copy_(C.new_tensor(p.C0))
         mg.sgemm_ws("T", "N", p.m, p.n, p.k, p.alpha, A, p.lda, B, p.ldb, p.beta, C, p.ldc, 1,
                     ws, need)
