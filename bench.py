@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the wide-range, rank-k, copy-bandwidth and 256^3 objects of the "
                          "default run")
+    ap.add_argument("--no-clock", action="store_true",
+                    help="skip the clock/power sampling runs (used under the profiler)")
     ap.add_argument("--no-peak", action="store_true",
                     help="skip the matrix-core rate probe in the default run")
     ap.add_argument("--problem", default="",
@@ -440,7 +442,7 @@ def cpu_baseline_leg(res, mg, torch, workload):
     return out, errors
 
 
-def batch_measure(torch, mg, problems, mode, steps, warmup):
+def batch_measure(torch, mg, problems, mode, steps, warmup, no_clock=False):
     """Plan the batch, capture one persistent launch in a HIP graph, replay
     it warmup + steps times; the replays of the timed region are bracketed
     by events on the replay stream."""
@@ -470,7 +472,7 @@ def batch_measure(torch, mg, problems, mode, steps, warmup):
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
     durs = [s.elapsed_time(e) for s, e in evs]
-    info["clock"] = clock_probe(torch, g.replay, seconds=1.5)
+    info["clock"] = None if no_clock else clock_probe(torch, g.replay, seconds=1.5)
     return res, plan, info, total, durs
 
 
@@ -511,7 +513,7 @@ def batch_line(args, torch, mg):
     cores = len(os.sched_getaffinity(0))
     for mode, name in ((mg.FP32, "fp32"), (mg.BF16X3, "bf16x3")):
         res, plan, info, total, durs = batch_measure(torch, mg, problems, mode, args.steps,
-                                                     args.warmup)
+                                                     args.warmup, args.no_clock)
         cfg = mg.config_info(info["config_id"])
         avg = float(np.mean(durs))
         out[name] = {"tflops": flops * args.steps / total / 1e12,
@@ -918,6 +920,20 @@ def event_median_ms(torch, fn, reps):
     return d[len(d) // 2], d[0]
 
 
+def warm(torch, fn, seconds=0.5):
+    """Run fn back to back for about `seconds`, so that a GPU that idled while
+    the host drew the next inputs is back at its working clock before the
+    timed calls (a cold GPU ran the first calls up to 15 % slower)."""
+    t0 = time.perf_counter()
+    n = 0
+    while time.perf_counter() - t0 < seconds:
+        fn()
+        n += 1
+        if n % 8 == 0:
+            torch.cuda.synchronize()
+    torch.cuda.synchronize()
+
+
 def copy_bandwidth(torch, nbytes=COPY_BYTES, reps=20):
     """Achievable HBM bandwidth on this GPU: a device-to-device copy of
     `nbytes` (4x the 256 MB Infinity Cache), read + write bytes over the
@@ -925,7 +941,7 @@ def copy_bandwidth(torch, nbytes=COPY_BYTES, reps=20):
     src = torch.empty(nbytes // 4, device="cuda:0")
     src.fill_(1.0)
     dst = torch.empty_like(src)
-    dst.copy_(src)
+    warm(torch, lambda: dst.copy_(src))
     med, best = event_median_ms(torch, lambda: dst.copy_(src), reps)
     del src, dst
     torch.cuda.empty_cache()
@@ -969,8 +985,7 @@ def wide_object(args, torch, mg, cores):
     out = {"workload": "8192^3 NN, alpha=1, beta=0, entries random sign x 2^U[-8,8] "
                        "(continuous U), both forms on the same inputs"}
     for mode, name in ((mg.FP32, "fp32"), (mg.BF16X3, "bf16x3")):
-        for _ in range(3):
-            r.call(mg, mode)
+        warm(torch, lambda: r.call(mg, mode))
         med, best = event_median_ms(torch, lambda: r.call(mg, mode), max(args.steps, 10))
         tf = flops / (med * 1e-3) / 1e12
         o = {"tflops": round(tf, 3), "ms": round(med, 4), "ms_min": round(best, 4)}
@@ -1011,8 +1026,7 @@ def rankk_object(args, torch, mg, copy_gbs, cores):
         row = {"k": k, "algorithmic_bytes": nbytes, "flops": flops}
         for mode, name, peak, mult in ((mg.FP32, "fp32", PEAK_FP32, 1),
                                        (mg.BF16X3, "bf16x3", PEAK_BF16, 6)):
-            for _ in range(3):
-                r.call(mg, mode)
+            warm(torch, lambda: r.call(mg, mode))
             med, _ = event_median_ms(torch, lambda: r.call(mg, mode), max(args.steps, 10))
             mfma_floor = mult * flops / (peak * 1e12) * 1e3
             hbm_floor = nbytes / (copy_gbs * 1e9) * 1e3
@@ -1042,8 +1056,7 @@ def c1_object(args, torch, mg):
     flops = 2.0 * r.p.m * r.p.n * r.p.k
     out = {"workload": "256^3 NN, alpha=1, beta=0, uniform[-1,1]"}
     for mode, name in ((mg.FP32, "fp32"), (mg.BF16X3, "bf16x3")):
-        for _ in range(20):
-            r.call(mg, mode)
+        warm(torch, lambda: r.call(mg, mode))
         lat = latency(torch, r, mg, mode)
         lat["tflops_at_median"] = round(flops / (lat["median_us"] * 1e-6) / 1e12, 3)
         lat["config"] = mg.config_info(mg.select_config("N", "N", 256, 256, 256, mode))["name"]
@@ -1104,7 +1117,8 @@ def main():
                         "dominant": "%dx%dx%d (%s)" % (dp.m, dp.n, dp.k,
                                                        ",".join(res[i].p.transa + res[i].p.transb
                                                                 for i in dominant)),
-                        "clock": clock_probe(torch, lambda: res[dominant[0]].call(mg, mode))}
+                        "clock": None if args.no_clock else
+                        clock_probe(torch, lambda: res[dominant[0]].call(mg, mode))}
     # per-problem rates (one extra timed pass each, after the timed region)
     per_problem = []
     for r in res:

@@ -65,6 +65,8 @@ def _bind(lib):
     lib.oracle_bf16x3_split_array.restype = None
     lib.oracle_bf16x3_sweep.argtypes = [ctypes.c_uint64, ctypes.c_uint64, vp, vp, i32]
     lib.oracle_bf16x3_sweep.restype = None
+    lib.oracle_bf16x3_split_digest.argtypes = [ctypes.c_uint64, ctypes.c_uint64, i32]
+    lib.oracle_bf16x3_split_digest.restype = ctypes.c_uint64
     f64 = ctypes.c_double
     lib.oracle_dgemm_f128.argtypes = [ctypes.c_char, ctypes.c_char, i64, i64, i64,
                                       f64, vp, i64, vp, i64, f64, vp, i64, vp, vp, i32]
@@ -248,6 +250,12 @@ class Oracle:
         return (int(counts[0]), int(counts[1]), int(counts[2]), int(counts[3]),
                 float(rel[0]), float(rel[1]))
 
+    def bf16x3_split_digest(self, lo: int, hi: int, nthreads: int = 0) -> int:
+        """Sum mod 2^64 of (p0 | p1 << 16 | p2 << 32) * (2u + 1) over the bit
+        patterns lo <= u < hi of the split's domain (finite, 2^-110 <= |x| <
+        0x1.fefp127): a digest of the split for comparing implementations."""
+        return int(self.lib.oracle_bf16x3_split_digest(lo, hi, nthreads))
+
 
 def _default() -> Oracle:
     global _lib
@@ -330,6 +338,10 @@ def bf16x3_split(x: np.ndarray) -> np.ndarray:
 
 def bf16x3_sweep(lo: int = 0, hi: int = 1 << 32, nthreads: int = 0):
     return _default().bf16x3_sweep(lo, hi, nthreads)
+
+
+def bf16x3_split_digest(lo: int, hi: int, nthreads: int = 0) -> int:
+    return _default().bf16x3_split_digest(lo, hi, nthreads)
 
 
 def bf16_to_f32(h: np.ndarray) -> np.ndarray:

@@ -252,6 +252,32 @@ void oracle_bf16x3_split_array(const float *x, int64_t count, uint16_t *parts)
 }
 
 /*
+ * Digest of the split over bit patterns lo <= u < hi, for comparing another
+ * implementation with this one over all 2^32 patterns without moving the
+ * parts: the sum, modulo 2^64, of (p0 | p1 << 16 | p2 << 32) * (2u + 1) over
+ * the patterns of the split's domain (finite, 2^-110 <= |x| < 0x1.fefp127,
+ * the domain of oracle_bf16x3_sweep), p0..p2 the bf16 parts of x.
+ */
+uint64_t oracle_bf16x3_split_digest(uint64_t lo, uint64_t hi, int nthreads)
+{
+    set_threads(nthreads);
+    uint64_t digest = 0;
+    const float lo_mag = ldexpf(1.0f, -110);
+    const float hi_mag = bits_f32(0x7f7f8000u);
+#pragma omp parallel for schedule(static) reduction(+:digest)
+    for (int64_t w = (int64_t)lo; w < (int64_t)hi; ++w) {
+        float x = bits_f32((uint32_t)w);
+        float ax = fabsf(x);
+        if (!(ax >= lo_mag && ax < hi_mag)) continue;
+        uint16_t p[3];
+        oracle_bf16x3_split(x, p);
+        const uint64_t key = (uint64_t)p[0] | ((uint64_t)p[1] << 16) | ((uint64_t)p[2] << 32);
+        digest += key * (2u * (uint64_t)w + 1u);
+    }
+    return digest;
+}
+
+/*
  * Exhaustive property sweep over all 2^32 FP32 bit patterns (parallel).
  * For every finite x with 2^-110 <= |x| < 0x1.fefp127 (below the value that
  * rounds to bf16 infinity) it checks:

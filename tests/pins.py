@@ -279,6 +279,27 @@ def pin_bf16x3_exhaustive(o, lo=0, hi=1 << 32):
     return checked, r1, r2
 
 
+def pin_bf16x3_digest(o, lo=0x3F000000, hi=0x3F000000 + (1 << 18)):
+    """The split digest equals its definition evaluated with numpy on the
+    oracle's own parts (the split is pinned above), on a range that also
+    holds patterns outside the domain (negative zero side, NaN/Inf are
+    excluded by the domain test)."""
+    total = 0
+    for a, b in ((lo, hi), (0x7F7F0000, 0x7F800010), (0x00000000, 0x00040000)):
+        u = np.arange(a, b, dtype=np.uint64)
+        x = u.astype(np.uint32).view(np.float32)
+        with np.errstate(invalid="ignore"):
+            ax = np.abs(x.astype(np.float64))
+        keep = (ax >= 2.0 ** -110) & (ax < float(np.uint32(0x7F7F8000).view(np.float32)))
+        parts = o.bf16x3_split(x[keep]).astype(np.uint64)
+        key = parts[:, 0] | (parts[:, 1] << np.uint64(16)) | (parts[:, 2] << np.uint64(32))
+        want = int(np.sum(key * (np.uint64(2) * u[keep] + np.uint64(1)), dtype=np.uint64))
+        got = o.bf16x3_split_digest(a, b)
+        assert got == want, (hex(a), got, want)
+        total += int(keep.sum())
+    assert total > 0
+
+
 def pin_bf16x3_method(o):
     """The split-precision oracle: (1) equals the FP64 oracle exactly on small
     integers (every part past the first is zero and all sums are exact);

@@ -162,6 +162,38 @@ def test_split_matches_oracle_bit_exact():
         x[bad[0]], got[bad[0]], ref[bad[0]])
 
 
+def test_split_exhaustive_against_oracle_digest():
+    """All 2^32 FP32 bit patterns through the GPU split, in chunks: for every
+    chunk the digest of the GPU parts over the split's domain (finite,
+    2^-110 <= |x| < 0x1.fefp127) equals the oracle's digest of its own
+    parts (sum mod 2^64 of (p0 | p1 << 16 | p2 << 32) * (2u + 1)); a
+    single differing part changes it."""
+    import torch
+    mg = _mg()
+    dev = torch.device("cuda:0")
+    chunk = 1 << 26
+    lo_mag = torch.tensor(2.0 ** -110, dtype=torch.float32, device=dev)
+    hi_mag = torch.tensor([0x7F7F8000], dtype=torch.int32).view(torch.float32).to(dev)
+    mod = 1 << 64
+    bad = []
+    for c in range((1 << 32) // chunk):
+        lo = c * chunk
+        u = torch.arange(lo, lo + chunk, dtype=torch.int64, device=dev)
+        x = torch.where(u >= (1 << 31), u - (1 << 32), u).to(torch.int32).view(torch.float32)
+        parts = torch.empty(3 * chunk, dtype=torch.int16, device=dev)
+        mg.bf16x3_split(x, chunk, parts)
+        ax = x.abs()
+        keep = (ax >= lo_mag) & (ax < hi_mag)
+        p = parts.view(chunk, 3).to(torch.int64) & 0xFFFF
+        key = p[:, 0] | (p[:, 1] << 16) | (p[:, 2] << 32)
+        got = int(torch.where(keep, key * (2 * u + 1), torch.zeros_like(key)).sum().item()) % mod
+        want = oracle.bf16x3_split_digest(lo, lo + chunk)
+        if got != want:
+            bad.append(hex(lo))
+        del u, x, parts, ax, keep, p, key
+    assert not bad, "split digests differ in the chunks starting at %s" % bad
+
+
 @pytest.mark.parametrize("mode", [0, 1], ids=["fp32", "bf16x3"])
 def test_degenerate_cases(mode):
     import torch

@@ -53,6 +53,10 @@ def test_bf16x3_split_exhaustive(o):
     assert checked > 3_800_000_000
 
 
+def test_bf16x3_split_digest(o):
+    pins.pin_bf16x3_digest(o)
+
+
 def test_bf16x3_method(o):
     pins.pin_bf16x3_method(o)
 
