@@ -1,17 +1,19 @@
 // Packed split-precision path: the BLIS packing step made explicit.
 //
 // pack_x3 turns op(A) (and op(B)) into "packed panels": for every block of
-// 16 consecutive k, for every part t of the bf16 split, for every row r (rows
-// padded to a multiple of PACK_ROWS, k padded to a multiple of 16, both with
-// zeros) the 16 bf16 values of that row, 32 contiguous bytes:
-//     P[((kb * 3 + t) * rows_pad + r) * 16 + (k % 16)]
+// 16 consecutive k, for every part t of the bf16 split, for each half h of
+// the block (k 0-7, k 8-15), for every row r (rows padded to a multiple of
+// PACK_ROWS, k padded to a multiple of 16, both with zeros) the 8 bf16 values
+// of that row, 16 contiguous bytes:
+//     P[(((kb * 3 + t) * 2 + h) * rows_pad + r) * 8 + (k % 8)]
 // The layout no longer depends on transposes or leading dimensions (as
 // BLIS's packed micro-panels, Section III-A of the paper), so one tile
 // kernel serves all four transpose pairs, with no masking in its main loop
-// and no split work between its MFMAs: a K block of a tile is three
-// contiguous runs of rows*32 bytes per operand, copied to LDS unchanged, and
-// 32 rows x 16 k of one part is exactly one 32x32x16 MFMA operand, read as a
-// contiguous kilobyte per wave.
+// and no split work between its MFMAs: a K block of a tile is six
+// contiguous runs of rows*16 bytes per operand, copied to LDS unchanged, and
+// 32 rows x 16 k of one part is exactly one 32x32x16 MFMA operand, which a
+// wave reads as two contiguous runs of 512 bytes (lanes 0-31 the low half of
+// k, lanes 32-63 the high half), free of LDS bank conflicts.
 #pragma once
 
 #include "gemm_tile.hpp"
@@ -76,9 +78,9 @@ __device__ __forceinline__ void pack_unit(const float *__restrict__ X, int64_t l
     }
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
-        __bf16 *dst = out + ((kb * 3 + t) * rows_pad + r) * PACK_K;
+        __bf16 *dst = out + ((kb * 3 + t) * 2 * rows_pad + r) * 8;
         *reinterpret_cast<bf16x8 *>(dst) = lo[t];
-        *reinterpret_cast<bf16x8 *>(dst + 8) = hi[t];
+        *reinterpret_cast<bf16x8 *>(dst + rows_pad * 8) = hi[t];
     }
 }
 
@@ -137,6 +139,20 @@ struct X3KTile {
         bf16x8 v[PPT];
     };
 
+    // Source of 16-byte piece q of K block kb: A pieces first, in the order
+    // part t, half h, row r (the order of the stage in LDS), then B.
+    __device__ __forceinline__ static const __bf16 *piece(const PackedArgs &p, int64_t m0,
+                                                         int64_t n0, int64_t kb, int q)
+    {
+        if (q < A_PIECES) {
+            const int t = q / (BM * 2), h = (q / BM) % 2, r = q % BM;
+            return p.Ap + (((kb * 3 + t) * 2 + h) * p.mp + m0 + r) * 8;
+        }
+        const int qb = q - A_PIECES;
+        const int t = qb / (BN * 2), h = (qb / BN) % 2, r = qb % BN;
+        return p.Bp + (((kb * 3 + t) * 2 + h) * p.np + n0 + r) * 8;
+    }
+
     __device__ __forceinline__ static void load(Stage &st, const PackedArgs &p, int64_t m0,
                                                 int64_t n0, int64_t kb, int tid)
     {
@@ -144,20 +160,12 @@ struct X3KTile {
         for (int s = 0; s < PPT; ++s) {
             const int q = tid + s * NT;
             const __bf16 *src;
-            if (q < A_PIECES) {
-                const int t = q / (BM * 2), w = q % (BM * 2);
-                src = p.Ap + ((kb * 3 + t) * p.mp + m0) * PACK_K + w * 8;
-            } else {
-                const int qb = q - A_PIECES;
-                const int t = qb / (BN * 2), w = qb % (BN * 2);
-                src = p.Bp + ((kb * 3 + t) * p.np + n0) * PACK_K + w * 8;
-            }
-            st.v[s] = *reinterpret_cast<const bf16x8 *>(src);
+            st.v[s] = *reinterpret_cast<const bf16x8 *>(piece(p, m0, n0, kb, q));
         }
     }
 
-    // LDS stage layout: A part t rows r at (t*BM + r)*16, then B likewise;
-    // piece q lands at q*8 halves, the same order as in the panels.
+    // LDS stage layout: A part t, half h, row r at ((t*2 + h)*BM + r)*8, then B
+    // likewise; piece q lands at q*8 halves.
     __device__ __forceinline__ static void store(const Stage &st, __bf16 *dst, int tid)
     {
 #pragma unroll
@@ -169,17 +177,17 @@ struct X3KTile {
                                                 __bf16 *nxt, const Stage &st, int tid, int wm,
                                                 int wn, int half, int l32)
     {
-        const __bf16 *As = cur + (wm * SH::WM + l32) * PACK_K + half * 8;
-        const __bf16 *Bs = cur + A_HALVES + (wn * SH::WN + l32) * PACK_K + half * 8;
+        const __bf16 *As = cur + (half * BM + wm * SH::WM + l32) * 8;
+        const __bf16 *Bs = cur + A_HALVES + (half * BN + wn * SH::WN + l32) * 8;
         bf16x8 a[RM][3], b[2][3];
 #pragma unroll
         for (int i = 0; i < RM; ++i)
 #pragma unroll
             for (int t = 0; t < 3; ++t)
-                a[i][t] = *reinterpret_cast<const bf16x8 *>(As + (t * BM + i * 32) * PACK_K);
+                a[i][t] = *reinterpret_cast<const bf16x8 *>(As + (t * 2 * BM + i * 32) * 8);
 #pragma unroll
         for (int t = 0; t < 3; ++t)
-            b[0][t] = *reinterpret_cast<const bf16x8 *>(Bs + t * BN * PACK_K);
+            b[0][t] = *reinterpret_cast<const bf16x8 *>(Bs + t * 2 * BN * 8);
         int q = 0;
 #pragma unroll
         for (int j = 0; j < RN; ++j) {
@@ -198,7 +206,7 @@ struct X3KTile {
 #pragma unroll
                         for (int t = 0; t < 3; ++t)
                             b[(j + 1) & 1][t] = *reinterpret_cast<const bf16x8 *>(
-                                Bs + (t * BN + (j + 1) * 32) * PACK_K);
+                                Bs + (t * 2 * BN + (j + 1) * 32) * 8);
                         __builtin_amdgcn_sched_barrier(0);
                     }
                     if (q == STORE_AT) {
@@ -216,17 +224,17 @@ struct X3KTile {
                                                         const __bf16 *cur, int tid, int wm,
                                                         int wn, int half, int l32)
     {
-        const __bf16 *As = cur + (wm * SH::WM + l32) * PACK_K + half * 8;
-        const __bf16 *Bs = cur + A_HALVES + (wn * SH::WN + l32) * PACK_K + half * 8;
+        const __bf16 *As = cur + (half * BM + wm * SH::WM + l32) * 8;
+        const __bf16 *Bs = cur + A_HALVES + (half * BN + wn * SH::WN + l32) * 8;
         bf16x8 a[RM][3], b[2][3];
 #pragma unroll
         for (int i = 0; i < RM; ++i)
 #pragma unroll
             for (int t = 0; t < 3; ++t)
-                a[i][t] = *reinterpret_cast<const bf16x8 *>(As + (t * BM + i * 32) * PACK_K);
+                a[i][t] = *reinterpret_cast<const bf16x8 *>(As + (t * 2 * BM + i * 32) * 8);
 #pragma unroll
         for (int t = 0; t < 3; ++t)
-            b[0][t] = *reinterpret_cast<const bf16x8 *>(Bs + t * BN * PACK_K);
+            b[0][t] = *reinterpret_cast<const bf16x8 *>(Bs + t * 2 * BN * 8);
         (void)tid;
 #pragma unroll
         for (int j = 0; j < RN; ++j) {
@@ -245,7 +253,7 @@ struct X3KTile {
 #pragma unroll
                         for (int t = 0; t < 3; ++t)
                             b[(j + 1) & 1][t] = *reinterpret_cast<const bf16x8 *>(
-                                Bs + (t * BN + (j + 1) * 32) * PACK_K);
+                                Bs + (t * 2 * BN + (j + 1) * 32) * 8);
                         __builtin_amdgcn_sched_barrier(0);
                     }
                 }
@@ -316,15 +324,7 @@ struct X3DTile {
 #pragma unroll
         for (int s = 0; s < PPT; ++s) {
             const int q = tid + s * NT;
-            const __bf16 *src;
-            if (q < K::A_PIECES) {
-                const int t = q / (SH::BM * 2), w = q % (SH::BM * 2);
-                src = p.Ap + ((kb * 3 + t) * p.mp + m0) * PACK_K + w * 8;
-            } else {
-                const int qb = q - K::A_PIECES;
-                const int t = qb / (SH::BN * 2), w = qb % (SH::BN * 2);
-                src = p.Bp + ((kb * 3 + t) * p.np + n0) * PACK_K + w * 8;
-            }
+            const __bf16 *src = K::piece(p, m0, n0, kb, q);
             __bf16 *dst = stage + (s * NT + wave * 64) * 8;  // wave-uniform base
             __builtin_amdgcn_global_load_lds((global_void_t *)src, (lds_void_t *)dst, 16, 0, 0);
         }
