@@ -1066,6 +1066,14 @@ def c1_object(args, torch, mg):
     return out
 
 
+def progress(msg):
+    """A stage of the run, on stderr (stdout carries only the JSON line)."""
+    print("bench: %s (%.0f s)" % (msg, time.perf_counter() - _T0), file=sys.stderr, flush=True)
+
+
+_T0 = time.perf_counter()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -1104,6 +1112,7 @@ def main():
     big = max(r.p.m * r.p.n * r.p.k for r in res)
     dominant = [i for i, r in enumerate(res) if r.p.m * r.p.n * r.p.k == big]
 
+    progress("inputs of %d problems resident" % len(res))
     result = {}
     for mode, name in ((mg.FP32, "fp32"), (mg.BF16X3, "bf16x3")):
         total, durs = time_steps(torch, res, mg, mode, args.steps, args.warmup, dominant)
@@ -1119,6 +1128,7 @@ def main():
                                                                 for i in dominant)),
                         "clock": None if args.no_clock else
                         clock_probe(torch, lambda: res[dominant[0]].call(mg, mode))}
+    progress("timed steps done")
     # per-problem rates (one extra timed pass each, after the timed region)
     per_problem = []
     for r in res:
@@ -1203,12 +1213,15 @@ def main():
         if (dp.m, dp.n, dp.k) == (8192, 8192, 8192) else None,
         "algorithmic_bytes_per_launch": 4.0 * (dp.m * dp.k + dp.k * dp.n + 2 * dp.m * dp.n),
     }
+    progress("per-problem rates done")
     if not args.no_cpu_baseline:
         cpu, errors = cpu_baseline_leg(res, mg, torch, args.workload)
+        progress("oracle leg done")
         line["cpu_baseline"] = cpu
         line["error"] = errors
     if args.workload == "square" and not args.no_peak:
         peaks = measure_peaks(torch)
+        progress("matrix-core peaks measured")
         line["measured_peak"] = peaks
         fp = peaks["fp32_random"]["tflops"]
         line["roofline"]["measured_peak"] = fp
@@ -1225,9 +1238,11 @@ def main():
         res = []
         cores = len(os.sched_getaffinity(0))
         line["wide8192"] = wide_object(args, torch, mg, cores)
+        progress("wide-range workload done")
         copy = copy_bandwidth(torch)
         line["hbm_copy"] = copy
         line["rankk"] = rankk_object(args, torch, mg, copy["gbs"], cores)
+        progress("rank-k workload done")
         line["c1"] = c1_object(args, torch, mg)
     if args.workload == "square" and not args.no_batch:
         del res

@@ -317,10 +317,13 @@ int misgemm_sgetrs(int64_t n, int64_t nrhs, const float *A, int64_t lda, const i
  * misgemm_sgemm / misgemm_dgemm on host matrices, synchronous: A and B are
  * copied into device buffers the library keeps per device (grow-only), C is
  * cut into column panels (about four when n >= 1024) and panel p+1 is copied
- * in while panel p is multiplied and panel p-1 copied back, on two streams
- * of the library's own.  Only the m rows of each column of C are written
- * (padding rows untouched) and nothing past the last column of any operand
- * is read.  Calls on one device are serialized.  Returns 0 or an error as
+ * in while panel p is multiplied and panel p-1 copied back, on three streams
+ * of the library's own; C's panels pass through pinned host buffers the
+ * library keeps per device (grow-only, hipHostMalloc), gathered from and
+ * scattered to the caller's columns by host threads.  Only the m rows of
+ * each column of C are written (padding rows untouched) and nothing past
+ * the last column of any operand is read.  Calls on one device are
+ * serialized.  Returns 0 or an error as
  * misgemm_sgemm / misgemm_dgemm (-14: mode).
  */
 int misgemm_sgemm_host(char transa, char transb, int64_t m, int64_t n, int64_t k,

@@ -13,6 +13,8 @@
 
 #include <algorithm>
 #include <mutex>
+#include <thread>
+#include <vector>
 
 #include "../../include/misgemm.h"
 
@@ -25,14 +27,18 @@ int trans_of(char t)
     return -1;
 }
 
-// Per-device state: two streams (copies, compute) and grow-only device
-// buffers for A, B and C.  Calls on one device are serialized.
+// Per-device state: three streams (copies in, compute, copies out), grow-only device buffers
+// for A, B and C, and grow-only pinned host buffers (two for C panels on
+// their way in, two on their way out) through which a C with padding rows
+// travels.  Calls on one device are serialized.
 struct HostState {
     std::mutex mu;
     bool init = false;
-    hipStream_t copy = nullptr, comp = nullptr;
+    hipStream_t copy = nullptr, comp = nullptr, out = nullptr;  // copies in, compute, copies out
     void *buf[3] = {nullptr, nullptr, nullptr};
     size_t cap[3] = {0, 0, 0};
+    void *pin[4] = {nullptr, nullptr, nullptr, nullptr};
+    size_t pin_cap[4] = {0, 0, 0, 0};
 };
 constexpr int MAX_DEV = 64;
 HostState g_host[MAX_DEV];
@@ -49,6 +55,51 @@ int ensure(HostState &h, int which, size_t bytes, void **out)
     }
     *out = h.buf[which];
     return 0;
+}
+
+// Pinned host buffer `which` of at least `bytes` (hipHostMalloc; the old one
+// is freed after the copy stream has drained, so no transfer still uses it).
+int ensure_pinned(HostState &h, int which, size_t bytes, void **out)
+{
+    if (h.pin_cap[which] < bytes) {
+        if (h.pin[which]) {
+            hipError_t e = hipStreamSynchronize(h.copy);
+            if (e == hipSuccess) e = hipStreamSynchronize(h.out);
+            if (e == hipSuccess) e = hipHostFree(h.pin[which]);
+            if (e != hipSuccess) return (int)e;
+        }
+        h.pin[which] = nullptr;
+        h.pin_cap[which] = 0;
+        const hipError_t e = hipHostMalloc(&h.pin[which], bytes, hipHostMallocDefault);
+        if (e != hipSuccess) return (int)e;
+        h.pin_cap[which] = bytes;
+    }
+    *out = h.pin[which];
+    return 0;
+}
+
+// The m rows of columns [0, cols) of a column-major host block (leading
+// dimension ld) to or from a contiguous m x cols buffer, on several host
+// threads for large blocks (plain memcpy per column).
+template <class T>
+void gather_columns(T *dst, const T *src, int64_t m, int64_t cols, int64_t ld, bool to_packed)
+{
+    const int64_t bytes = m * cols * (int64_t)sizeof(T);
+    const int nt = bytes >= ((int64_t)8 << 20) ? 8 : 1;
+    auto work = [&](int t) {
+        for (int64_t c = t; c < cols; c += nt) {
+            if (to_packed) memcpy(dst + c * m, src + c * ld, (size_t)m * sizeof(T));
+            else memcpy(dst + c * ld, src + c * m, (size_t)m * sizeof(T));
+        }
+    };
+    if (nt == 1) {
+        work(0);
+        return;
+    }
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nt; ++t) pool.emplace_back(work, t);
+    work(0);
+    for (auto &th : pool) th.join();
 }
 
 // Copy the rows x cols column-major block with leading dimension ld
@@ -106,7 +157,8 @@ int host_gemm(char transa, char transb, int64_t m, int64_t n, int64_t k, T alpha
     std::lock_guard<std::mutex> lock(h.mu);
     if (!h.init) {
         if (hipStreamCreateWithFlags(&h.copy, hipStreamNonBlocking) != hipSuccess ||
-            hipStreamCreateWithFlags(&h.comp, hipStreamNonBlocking) != hipSuccess)
+            hipStreamCreateWithFlags(&h.comp, hipStreamNonBlocking) != hipSuccess ||
+            hipStreamCreateWithFlags(&h.out, hipStreamNonBlocking) != hipSuccess)
             return MISGEMM_E_NO_DEVICE;
         h.init = true;
     }
@@ -129,23 +181,68 @@ int host_gemm(char transa, char transb, int64_t m, int64_t n, int64_t k, T alpha
     }
     const int64_t nb = panel_width(n);
     const int64_t panels = (n + nb - 1) / nb;
+    // C's panels go through pinned buffers, gathered and scattered by host
+    // threads (only the m rows of each column: the padding of a host C may
+    // belong to a larger matrix and must not be written), so the DMA engines
+    // move contiguous pinned data: a column-wise copy from pageable memory
+    // ran at 4-6 GB/s, a contiguous one (tight ldc) at about 20 GB/s.  Panel
+    // p's gather happens while panel p-1 is multiplied, its scatter while
+    // panel p+1 is.
+    const bool staged = true;
+    T *pin_in[2] = {nullptr, nullptr}, *pin_out[2] = {nullptr, nullptr};
+    if (staged) {
+        const size_t pbytes = (size_t)m * nb * sizeof(T);
+        for (int i = 0; i < 4 && rc == 0; ++i) {
+            void *ptr = nullptr;
+            if (i < 2 && beta == T(0)) continue;  // C0 is not read
+            rc = ensure_pinned(h, i, pbytes, &ptr);
+            (i < 2 ? pin_in[i] : pin_out[i - 2]) = (T *)ptr;
+        }
+        if (rc != 0) return rc;
+    }
     constexpr int nev = 4;
-    hipEvent_t in_done[nev] = {}, out_done[nev] = {};
+    hipEvent_t in_done[nev] = {}, out_done[nev] = {}, pin_free[2] = {}, pin_full[2] = {};
     for (int i = 0; i < nev && e == hipSuccess; ++i) {
         e = hipEventCreateWithFlags(&in_done[i], hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&out_done[i], hipEventDisableTiming);
     }
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+        e = hipEventCreateWithFlags(&pin_free[i], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&pin_full[i], hipEventDisableTiming);
+    }
+    bool pin_in_used[2] = {false, false};
+    auto scatter = [&](int64_t q) -> hipError_t {
+        // panel q's result, copied into pin_out[q % 2], to the host C
+        const int64_t q0 = q * nb, qc = std::min(nb, n - q0);
+        const hipError_t se = hipEventSynchronize(pin_full[q % 2]);
+        if (se == hipSuccess) gather_columns(C + q0 * ldc, pin_out[q % 2], m, qc, ldc, false);
+        return se;
+    };
     for (int64_t p = 0; p < panels && e == hipSuccess && rc == 0; ++p) {
         const int64_t j0 = p * nb, cols = std::min(nb, n - j0);
-        const int slot = (int)(p % nev);
+        const int slot = (int)(p % nev), ps = (int)(p % 2);
         // stage panel p (its own device columns, so no panel waits for
         // another): B columns (transb = N), C columns when beta != 0
         if (reads_ab && !tb)
             e = copy_block(b + j0 * ldb, B + j0 * ldb, brows, cols, ldb, hipMemcpyHostToDevice,
                            h.copy, true);
-        if (e == hipSuccess && beta != T(0))
-            e = copy_block(c + j0 * ldc, C + j0 * ldc, m, cols, ldc, hipMemcpyHostToDevice,
-                           h.copy, false);
+        if (e == hipSuccess && beta != T(0)) {
+            if (staged) {
+                // the pinned buffer's previous transfer (panel p-2) must be done
+                if (pin_in_used[ps]) e = hipEventSynchronize(pin_free[ps]);
+                if (e == hipSuccess) {
+                    gather_columns(pin_in[ps], C + j0 * ldc, m, cols, ldc, true);
+                    e = hipMemcpy2DAsync(c + j0 * ldc, (size_t)ldc * sizeof(T), pin_in[ps],
+                                         (size_t)m * sizeof(T), (size_t)m * sizeof(T),
+                                         (size_t)cols, hipMemcpyHostToDevice, h.copy);
+                }
+                if (e == hipSuccess) e = hipEventRecord(pin_free[ps], h.copy);
+                pin_in_used[ps] = true;
+            } else {
+                e = copy_block(c + j0 * ldc, C + j0 * ldc, m, cols, ldc, hipMemcpyHostToDevice,
+                               h.copy, false);
+            }
+        }
         if (e == hipSuccess) e = hipEventRecord(in_done[slot], h.copy);
         if (e == hipSuccess) e = hipStreamWaitEvent(h.comp, in_done[slot], 0);
         if (e != hipSuccess) break;
@@ -154,23 +251,41 @@ int host_gemm(char transa, char transb, int64_t m, int64_t n, int64_t k, T alpha
         rc = gemm(transa, transb, m, cols, k, alpha, a, lda, bp, ldb, beta, c + j0 * ldc, ldc,
                   (void *)h.comp);
         if (rc != 0) break;
+        // copy panel p back on its own stream (only its m rows: the host
+        // padding stays untouched), so the next panel's inputs need not wait
+        // for it
         e = hipEventRecord(out_done[slot], h.comp);
-        if (e == hipSuccess) e = hipStreamWaitEvent(h.copy, out_done[slot], 0);
-        // copy panel p back (only its m rows: the host padding stays untouched)
-        if (e == hipSuccess)
-            e = copy_block(C + j0 * ldc, c + j0 * ldc, m, cols, ldc, hipMemcpyDeviceToHost,
-                           h.copy, false);
-        if (e == hipSuccess) e = hipEventRecord(out_done[slot], h.copy);
+        if (e == hipSuccess) e = hipStreamWaitEvent(h.out, out_done[slot], 0);
+        if (e == hipSuccess) {
+            if (staged) {
+                e = hipMemcpy2DAsync(pin_out[ps], (size_t)m * sizeof(T), c + j0 * ldc,
+                                     (size_t)ldc * sizeof(T), (size_t)m * sizeof(T),
+                                     (size_t)cols, hipMemcpyDeviceToHost, h.out);
+                if (e == hipSuccess) e = hipEventRecord(pin_full[ps], h.out);
+                // the previous panel's result goes to C while this one is computed
+                if (e == hipSuccess && p > 0) e = scatter(p - 1);
+            } else {
+                e = copy_block(C + j0 * ldc, c + j0 * ldc, m, cols, ldc, hipMemcpyDeviceToHost,
+                               h.out, false);
+            }
+        }
     }
+    if (staged && e == hipSuccess && rc == 0 && panels > 0) e = scatter(panels - 1);
     const hipError_t s1 = hipStreamSynchronize(h.comp), s2 = hipStreamSynchronize(h.copy);
+    const hipError_t s3 = hipStreamSynchronize(h.out);
     for (int i = 0; i < nev; ++i) {
         if (in_done[i]) (void)hipEventDestroy(in_done[i]);
         if (out_done[i]) (void)hipEventDestroy(out_done[i]);
     }
+    for (int i = 0; i < 2; ++i) {
+        if (pin_free[i]) (void)hipEventDestroy(pin_free[i]);
+        if (pin_full[i]) (void)hipEventDestroy(pin_full[i]);
+    }
     if (rc != 0) return rc;
     if (e != hipSuccess) return (int)e;
     if (s1 != hipSuccess) return (int)s1;
-    return (int)s2;
+    if (s2 != hipSuccess) return (int)s2;
+    return (int)s3;
 }
 
 void report(const char *name, int rc)
