@@ -301,8 +301,9 @@ class Resident:
 
 
 def time_steps(torch, res, mg, mode, steps, warmup, dominant):
-    """Run warmup + steps passes; returns (total seconds, dominant-kernel
-    launch durations in ms).  The dominant kernel is timed with events on
+    """Run warmup passes, then about 0.3 s more of them to bring the GPU to
+    its working clock (when warmup > 0), then `steps` timed passes; returns
+    (total seconds, dominant-kernel launch durations in ms).  The dominant kernel is timed with events on
     the stream the library launches on (torch's current stream), on every
     step, or every 8th when the workload is a single problem."""
     stream = torch.cuda.current_stream()
@@ -310,6 +311,8 @@ def time_steps(torch, res, mg, mode, steps, warmup, dominant):
         for r in res:
             r.call(mg, mode)
     torch.cuda.synchronize()
+    if warmup > 0:
+        warm(torch, lambda: [r.call(mg, mode) for r in res], seconds=0.3)
     ev = []
     # a one-problem workload (the 256^3 case) would time the event records
     # along with each microsecond-scale call: sample every 8th step there
@@ -459,6 +462,8 @@ def batch_measure(torch, mg, problems, mode, steps, warmup, no_clock=False):
     for _ in range(warmup):
         g.replay()
     torch.cuda.synchronize()
+    if warmup > 0:
+        warm(torch, g.replay, seconds=0.3)
     stream = torch.cuda.current_stream()
     evs = []
     t0 = time.perf_counter()

@@ -4,6 +4,8 @@
     python -m paper_1608_05265_amd.profsummary pmc <dir-with-counter_collection.csv>
     python -m paper_1608_05265_amd.profsummary dispatch <dir-with-counter_collection.csv>
     python -m paper_1608_05265_amd.profsummary bytes <read-dir> <write-dir>
+    python -m paper_1608_05265_amd.profsummary traffic <fetch-dir> <write-dir> \
+        <read-req-dir> <write-req-dir> <kernel-regex> [<form> <hash>]
 
 `trace` groups dispatches by kernel and grid size and prints calls, average,
 minimum and maximum duration in microseconds; `pmc` prints the per-dispatch
@@ -14,7 +16,12 @@ counter sums the cycles of every SIMD, GRBM_GUI_ACTIVE sums the active
 cycles of the 8 XCDs; 1024 SIMDs on MI355X); `dispatch` prints every
 dispatch with its counters (for calibration runs that mix kernels of one
 name); `bytes` turns the L2-to-memory request counters of two runs into
-bytes per dispatch (below).
+bytes per dispatch (below); `traffic` sums, over the kernels whose short
+name matches the regex (the kernels of one call or one launch, each run
+once per call), the per-dispatch means of FETCH_SIZE and WRITE_SIZE, scaled
+by their readings for a plain copy of known size, and of the request bytes,
+and with a form name and a source hash prints them as the
+`traffic_bytes_per_launch` and `ea_bytes_per_launch` lines bench.py reads.
 Kernel names are shortened to the template arguments that identify a tile
 configuration.
 """
@@ -184,10 +191,78 @@ def bytes_summary(read_dir: str, write_dir: str):
     return "\n".join(out)
 
 
+COPY_KIB = 1048576.0  # the 1 GiB device-to-device copy bench.py runs for calibration
+
+
+def _counter_means(d: str, counter: str, pattern):
+    """Per (kernel, grid) whose short name matches: mean of one counter."""
+    groups = collections.OrderedDict()
+    for name, grid, c in _per_dispatch(d).values():
+        if pattern.search(name):
+            groups.setdefault((name, grid), []).append(c[counter])
+    return {k: sum(v) / len(v) for k, v in groups.items()}
+
+
+def copy_scale(d: str, counter: str, default: float) -> float:
+    """COPY_KIB over the counter's mean reading for the 1 GiB copies of the
+    run (the copy dispatches with the largest reading), else `default`."""
+    vals = [c[counter] for name, grid, c in _per_dispatch(d).values()
+            if name.startswith("__amd_rocclr_copyBuffer")]
+    if not vals:
+        return default
+    top = max(vals)
+    big = [v for v in vals if v > 0.9 * top]
+    mean = sum(big) / len(big)
+    return COPY_KIB / mean if mean > 0.25 * COPY_KIB else default
+
+
+def traffic_summary(fetch_dir, write_dir, rd_dir, wr_dir, regex, form=None, src_hash=None):
+    pat = re.compile(regex)
+    fs = copy_scale(fetch_dir, "FETCH_SIZE", 2.0)
+    ws = copy_scale(write_dir, "WRITE_SIZE", 1.0)
+    fetch = _counter_means(fetch_dir, "FETCH_SIZE", pat)
+    write = _counter_means(write_dir, "WRITE_SIZE", pat)
+    rd = collections.OrderedDict()
+    for name, grid, c in _per_dispatch(rd_dir).values():
+        if pat.search(name):
+            rd.setdefault((name, grid), []).append(read_bytes(c))
+    wr = collections.OrderedDict()
+    for name, grid, c in _per_dispatch(wr_dir).values():
+        if pat.search(name):
+            wr.setdefault((name, grid), []).append(write_bytes(c))
+
+    def m(v, i):
+        return sum(x[i] for x in v) / len(v)
+    out = ["copy calibration: FETCH_SIZE x%.3f, WRITE_SIZE x%.3f" % (fs, ws),
+           "%-58s %-10s %12s %12s %12s %12s %12s %12s" % (
+               "kernel", "grid", "fetch_KiB", "write_KiB", "read_B", "read_dram_B",
+               "write_B", "write_dram_B")]
+    tot = [0.0] * 6
+    for key in fetch:
+        row = [fetch.get(key, 0.0), write.get(key, 0.0),
+               m(rd[key], 0) if key in rd else 0.0, m(rd[key], 1) if key in rd else 0.0,
+               m(wr[key], 0) if key in wr else 0.0, m(wr[key], 1) if key in wr else 0.0]
+        tot = [a + b for a, b in zip(tot, row)]
+        out.append("%-58s %-10s %12.1f %12.1f %12.4e %12.4e %12.4e %12.4e" % (
+            (key[0], key[1]) + tuple(row)))
+    scaled = 1024.0 * (fs * tot[0] + ws * tot[1])
+    out.append("per call (sum of the rows): fetch %.1f KiB x%.3f + write %.1f KiB x%.3f = "
+               "%.4e B; requests: read %.4e B (%.4e to memory), write %.4e B (%.4e to memory)"
+               % (tot[0], fs, tot[1], ws, scaled, tot[2], tot[3], tot[4], tot[5]))
+    if form and src_hash:
+        out.append("traffic_bytes_per_launch %s %s %.4e" % (form, src_hash, scaled))
+        out.append("ea_bytes_per_launch %s %s %.4e %.4e %.4e %.4e" % (
+            form, src_hash, tot[2], tot[3], tot[4], tot[5]))
+    return "\n".join(out)
+
+
 def main(argv=None):
     argv = sys.argv[1:] if argv is None else argv
     if len(argv) == 3 and argv[0] == "bytes":
         print(bytes_summary(argv[1], argv[2]))
+        return 0
+    if len(argv) in (6, 8) and argv[0] == "traffic":
+        print(traffic_summary(*argv[1:]))
         return 0
     if len(argv) != 2 or argv[0] not in ("trace", "pmc", "dispatch"):
         print(__doc__)
