@@ -303,9 +303,10 @@ class Resident:
 def time_steps(torch, res, mg, mode, steps, warmup, dominant):
     """Run warmup passes, then about 0.3 s more of them to bring the GPU to
     its working clock (when warmup > 0), then `steps` timed passes; returns
-    (total seconds, dominant-kernel launch durations in ms).  The dominant kernel is timed with events on
-    the stream the library launches on (torch's current stream), on every
-    step, or every 8th when the workload is a single problem."""
+    (total seconds, dominant-kernel launch durations in ms).  The dominant
+    kernel is timed with events on the stream the library launches on
+    (torch's current stream), on every step, or every 8th when the workload
+    is a single problem."""
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
         for r in res:
@@ -829,7 +830,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sgemm_dominant8192_hbm_counters.t
 BATCH_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "batch512_kernel_trace.txt")
 # what decides the sgemm kernels and which of them runs: their sources and
 # the packaged tuning table
-KERNEL_SOURCES = ["gemm_tile.hpp", "packed_x3.hpp", "registry.hpp", "aux_kernels.hip",
+KERNEL_SOURCES = ["gemm_tile.hpp", "gemm_rtile.hpp", "packed_x3.hpp", "registry.hpp", "aux_kernels.hip",
                   "sgemm_f32.hip", "sgemm_x3.hip", "sgemm_x3k.hip"]
 # host code that decides what the kernels touch and in which order (tile
 # choice, tile order, the batch plan's tile lists), hashed with the kernels

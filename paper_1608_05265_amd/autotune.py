@@ -221,16 +221,73 @@ def write_table(path, gemm_rows, batch):
                         % r["tflops"])
 
 
+def merge_table(base_path, out_path, gemm_rows):
+    """Write base_path to out_path with the entries (and their comment
+    lines) of every key in gemm_rows replaced by the new rows, placed where
+    the key's first old entry was (new keys go after the last entry)."""
+    new = {}
+    for r in gemm_rows:
+        new.setdefault((r["mode"], r["ta"], r["tb"], r["m"], r["n"], r["k"]), []).append(r)
+
+    def fmt(r):
+        return ["%d %s %s %d %d %d %s %d %d\n" % (r["mode"], r["ta"], r["tb"], r["m"], r["n"],
+                                                r["k"], r["config"], r["group_m"],
+                                                r.get("splits", 1)),
+                "#   %.1f TFLOP/s\n" % r["tflops"]]
+    out, done, skipping, last_entry = [], set(), False, 0
+    with open(base_path) as f:
+        lines = f.readlines()
+    for line in lines:
+        parts = line.split()
+        if line.startswith("#") and skipping:
+            continue
+        skipping = False
+        if len(parts) == 9 and parts[0] in ("0", "1"):
+            key = (int(parts[0]), parts[1], parts[2], int(parts[3]), int(parts[4]), int(parts[5]))
+            if key in new:
+                skipping = True
+                if key not in done:
+                    done.add(key)
+                    for r in new[key]:
+                        out.extend(fmt(r))
+                    last_entry = len(out)
+                continue
+            out.append(line)
+            last_entry = len(out)
+            continue
+        out.append(line)
+    rest = [ln for key, rows in new.items() if key not in done for r in rows for ln in fmt(r)]
+    out[last_entry:last_entry] = rest
+    with open(out_path, "w") as f:
+        f.writelines(out)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                                    "tuning_mi355x.txt"))
     ap.add_argument("--json", default=None, help="also dump every timing here")
     ap.add_argument("--quick", action="store_true", help="fewer keys (smoke test of the tuner)")
+    ap.add_argument("--sizes", default=None,
+                    help="comma list: tune only the square keys of these sizes and merge the "
+                         "rows into the table named by --merge (no batch tuning)")
+    ap.add_argument("--rankk", action="store_true",
+                    help="with --merge: also tune the 16384^2 x K rank-k keys")
+    ap.add_argument("--merge", default=None, help="table to merge --sizes rows into")
     args = ap.parse_args(argv)
     os.environ["MISGEMM_TUNING"] = "none"  # tune from the built-in defaults
     from paper_1608_05265_amd import workloads as wl
     keys = default_keys()
+    if args.sizes or args.rankk:
+        if not args.merge:
+            ap.error("--sizes and --rankk need --merge")
+        sizes = {int(v) for v in args.sizes.split(",")} if args.sizes else set()
+        keys = [k for k in keys if (k[3] == k[4] == k[5] and k[3] in sizes) or
+                (args.rankk and k[3] == k[4] == 16384 and k[5] in wl.RANKK_KS)]
+        rows = tune_gemm(keys, log=lambda s: print(s, flush=True))
+        merge_table(args.merge, args.out, rows)
+        print("wrote", args.out)
+        return 0
     if args.quick:
         keys = [k for k in keys if k[3] <= 1024 and k[5] <= 1024][:6]
     rows = tune_gemm(keys, log=lambda s: print(s, flush=True))

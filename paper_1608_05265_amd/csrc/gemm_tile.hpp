@@ -264,6 +264,15 @@ struct StageX3 {
 // 8g + 4*(l/32) + e, column l % 32, so each lane owns four consecutive rows
 // of one column (one 16-byte store in column-major C).
 // ---------------------------------------------------------------------------
+// beta == 0: C0 is not read.  C0 and C are one array, so as far as the
+// compiler knows a store may alias any later load, and no load moves above
+// an earlier store: loaded one 16-byte group at a time, every group would
+// cost the wave a full memory round trip.  The C0 loads of EPI_GROUP groups
+// are therefore issued together ahead of their stores (one round trip per
+// EPI_GROUP groups, 4 * EPI_GROUP more VGPRs; 4 keeps the 128x128 tiles at
+// three waves per SIMD, 8 does not).
+constexpr int EPI_GROUP = 4;
+
 template <int RM, int RN>
 __device__ __forceinline__ void epilogue(const GemmArgs &g, const floatx16 (&acc)[RM][RN],
                                          int64_t row0, int64_t col0, int lane)
@@ -271,36 +280,45 @@ __device__ __forceinline__ void epilogue(const GemmArgs &g, const floatx16 (&acc
     const int half = lane >> 5, l32 = lane & 31;
     const bool vec = g.vec_c;
     const bool use_c0 = g.beta != 0.0f;
+    constexpr int NG = RN * RM * 4;                       // 16-byte groups per lane
+    constexpr int GG = EPI_GROUP < NG ? EPI_GROUP : NG;
+    static_assert(NG % GG == 0, "whole load groups");
 #pragma unroll
-    for (int rn = 0; rn < RN; ++rn) {
-        const int64_t col = col0 + rn * 32 + l32;
-        if (col >= g.n) continue;
-        float *cc = g.C + col * g.ldc;
+    for (int g0 = 0; g0 < NG; g0 += GG) {
+        floatx4 c0[GG];
 #pragma unroll
-        for (int rm = 0; rm < RM; ++rm) {
+        for (int q = 0; q < GG; ++q) {
+            const int idx = g0 + q, rn = idx / (RM * 4), rm = (idx / 4) % RM, gi = idx % 4;
+            const int64_t col = col0 + rn * 32 + l32;
+            const int64_t row = row0 + rm * 32 + gi * 8 + half * 4;
 #pragma unroll
-            for (int gi = 0; gi < 4; ++gi) {
-                const int64_t row = row0 + rm * 32 + gi * 8 + half * 4;
-                if (row >= g.m) continue;
-                float *p = cc + row;
-                floatx4 out;
+            for (int e = 0; e < 4; ++e) c0[q][e] = 0.0f;
+            if (use_c0 && vec && col < g.n && row + 4 <= g.m)
+                c0[q] = *reinterpret_cast<const floatx4 *>(g.C + col * g.ldc + row);
+        }
 #pragma unroll
-                for (int e = 0; e < 4; ++e) out[e] = g.alpha * acc[rm][rn][gi * 4 + e];
-                if (vec && row + 4 <= g.m) {
-                    if (use_c0) {
-                        const floatx4 c0 = *reinterpret_cast<const floatx4 *>(p);
+        for (int q = 0; q < GG; ++q) {
+            const int idx = g0 + q, rn = idx / (RM * 4), rm = (idx / 4) % RM, gi = idx % 4;
+            const int64_t col = col0 + rn * 32 + l32;
+            const int64_t row = row0 + rm * 32 + gi * 8 + half * 4;
+            if (col >= g.n || row >= g.m) continue;
+            float *p = g.C + col * g.ldc + row;
+            floatx4 out;
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) out[e] += g.beta * c0[e];
-                    }
-                    *reinterpret_cast<floatx4 *>(p) = out;
-                } else {
+            for (int e = 0; e < 4; ++e) out[e] = g.alpha * acc[rm][rn][gi * 4 + e];
+            if (vec && row + 4 <= g.m) {
+                if (use_c0) {
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        if (row + e < g.m) {
-                            float o = out[e];
-                            if (use_c0) o += g.beta * p[e];
-                            p[e] = o;
-                        }
+                    for (int e = 0; e < 4; ++e) out[e] += g.beta * c0[q][e];
+                }
+                *reinterpret_cast<floatx4 *>(p) = out;
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    if (row + e < g.m) {
+                        float o = out[e];
+                        if (use_c0) o += g.beta * p[e];
+                        p[e] = o;
                     }
                 }
             }

@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "../../include/misgemm.h"
+#include "gemm_rtile.hpp"
 #include "gemm_tile.hpp"
 #include "packed_x3.hpp"
 

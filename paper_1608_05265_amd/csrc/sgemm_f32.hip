@@ -1,4 +1,5 @@
-// FP32 matrix-core configurations (v_mfma_f32_32x32x2_f32).
+// FP32 matrix-core configurations (v_mfma_f32_32x32x2_f32; the register
+// tiles v_mfma_f32_16x16x4_f32).
 #include <string.h>
 
 #include "registry.hpp"
@@ -16,6 +17,9 @@ using F32W = F32WTile<SH, TA, TB>;
 // global loads two K blocks ahead (two register sets)
 template <class SH, bool TA, bool TB>
 using F32Q = F32Tile<SH, TA, TB, true>;
+// register tiles (16x16 blocks, no LDS staging) for latency-bound problems
+template <class SH, bool TA, bool TB>
+using F32R = F32RTile<SH, TA, TB>;
 
 template <template <class, bool, bool> class T, class SH, bool BATCHED, bool SPLITK = false>
 ConfigEntry make_f32(const char *name)
@@ -67,6 +71,9 @@ void register_f32(std::vector<ConfigEntry> &out)
     // small tiles, four waves splitting each tile's K steps
     out.push_back(make_f32<F32W, WShape<64, 64, 32, 4>, true>("fp32w_64x64x32_k4"));
     out.push_back(make_f32<F32W, WShape<32, 32, 32, 4>, true>("fp32w_32x32x32_k4"));
+    // register tiles: four waves take 64-k chunks in turn
+    out.push_back(make_f32<F32R, RShape<16, 16, 4>, false>("fp32r_16x16x64_r4"));
+    out.push_back(make_f32<F32R, RShape<32, 32, 4>, true>("fp32r_32x32x64_r4"));
 }
 
 }  // namespace misgemm

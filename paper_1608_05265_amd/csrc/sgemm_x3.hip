@@ -29,6 +29,11 @@ using X3Q13 = X3PTile<SH, TA, TB, 1, 3, false, true>;
 template <class SH, bool TA, bool TB>
 using X3W = X3WTile<SH, TA, TB>;
 
+// register tiles (16x16 blocks on v_mfma_f32_16x16x32_bf16, split in
+// registers, no LDS staging) for latency-bound problems
+template <class SH, bool TA, bool TB>
+using X3R = X3RTile<SH, TA, TB>;
+
 template <template <class, bool, bool> class T, class SH, bool BATCHED, bool SPLITK = false>
 ConfigEntry make_x3(const char *name)
 {
@@ -75,6 +80,9 @@ void register_x3(std::vector<ConfigEntry> &out)
     out.push_back(make_x3<X3S, Shape<64, 64, 32, 32, 32>, true, true>("x3_64x64x32_w32x32"));
     out.push_back(make_x3<X3W, WShape<64, 64, 64, 4>, true>("x3w_64x64x64_k4"));
     out.push_back(make_x3<X3W, WShape<32, 32, 64, 4>, true>("x3w_32x32x64_k4"));
+    // register tiles: four waves take 64-k chunks in turn
+    out.push_back(make_x3<X3R, RShape<16, 16, 4>, false>("x3r_16x16x64_r4"));
+    out.push_back(make_x3<X3R, RShape<32, 32, 4>, true>("x3r_32x32x64_r4"));
 }
 
 }  // namespace misgemm

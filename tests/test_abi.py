@@ -45,7 +45,7 @@ def test_configs_and_strings(mg):
     names = set()
     for c in mg.configs():
         assert c["mode"] in (0, 1)
-        assert c["bm"] % 32 == 0 and c["bn"] % 32 == 0 and c["threads"] % 64 == 0
+        assert c["bm"] % 16 == 0 and c["bn"] % 16 == 0 and c["threads"] % 64 == 0
         assert 0 < c["lds_bytes"] <= 160 * 1024
         names.add(c["name"])
     assert len(names) == n

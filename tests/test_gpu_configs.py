@@ -109,14 +109,16 @@ def test_same_sign_long_k_every_config():
             print("same-sign K=8192 %s mode %d: max %.3e mean %.3e (%.2e of bound)"
                   % (name, mode, mx, mean, ratio))
     # K schedules: "default" (the dispatcher's choice), "kW" for the small
-    # tiles whose W waves take every W-th k step (names ending in _kW), and
-    # "whole" (one accumulator over k in order) for every other tile; native
-    # configurations with the same schedule give the same bits
+    # tiles whose W waves take every W-th k step (names ending in _kW), "rW"
+    # for the register tiles whose W waves take every W-th 64-k chunk (names
+    # ending in _rW), and "whole" (one accumulator over k in order) for every
+    # other tile; native configurations with the same schedule give the same
+    # bits
     def schedule(name):
         if name == "default":
             return name
         tail = name.rsplit("_", 1)[-1]
-        return tail if tail[0] == "k" and tail[1:].isdigit() else "whole"
+        return tail if tail[0] in "kr" and tail[1:].isdigit() else "whole"
     native = {}
     for (mode, name), v in err.items():
         if mode == 0:

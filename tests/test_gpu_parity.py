@@ -49,6 +49,20 @@ def test_every_config_every_transpose():
             gu.check_full(p, out, "%s %s%s" % (cfg["name"], ta, tb))
 
 
+def test_every_config_whole_blocks_with_beta():
+    """Every configuration on a problem of whole tiles and whole K blocks
+    (the unmasked load path) with beta != 0, each transpose pair: the paths
+    that read C0 early, fold it into the accumulators or skip masking are
+    all taken here."""
+    mg = _mg()
+    for cfg in mg.configs():
+        for ti, (ta, tb) in enumerate(wl.TRANS_PAIRS):
+            m, n, k = 2 * cfg["bm"], 2 * cfg["bn"], 8 * cfg["bk"]
+            p = wl.make_problem(ta, tb, m, n, k, -1.5, 0.75, 3000 + 4 * cfg["id"] + ti)
+            out = gu.run(p, cfg["mode"], config_id=cfg["id"])
+            gu.check_full(p, out, "%s %s%s whole blocks" % (cfg["name"], ta, tb))
+
+
 @pytest.mark.parametrize("mode", [0, 1], ids=["fp32", "bf16x3"])
 def test_integer_inputs_bit_exact(mode):
     """Entries in {-4..4}, K <= 1024: every partial sum is an exact integer
