@@ -210,21 +210,26 @@ def write_table(path, gemm_rows, batch):
                                                       r["k"], r["config"], r["group_m"],
                                                       r.get("splits", 1)))
             f.write("#   %.1f TFLOP/s\n" % r["tflops"])
-        for mode, b in sorted(batch.items()):
-            f.write("batch %d %s\n" % (mode, b["config"]))
-            f.write("#   %.1f TFLOP/s on a 512-problem batch of the benchmark's distribution "
-                    "(other seeds)\n" % b["tflops"])
-            if "rule" in b:
-                r = b["rule"]
-                f.write("batch2 %d %d %s %s\n" % (mode, r["threshold"], r["big"], r["small"]))
-                f.write("#   %.1f TFLOP/s on that batch, two concurrent parts\n"
-                        % r["tflops"])
+        write_batch_lines(f, batch)
 
 
-def merge_table(base_path, out_path, gemm_rows):
+def write_batch_lines(f, batch):
+    for mode, b in sorted(batch.items()):
+        f.write("batch %d %s\n" % (mode, b["config"]))
+        f.write("#   %.1f TFLOP/s on a 512-problem batch of the benchmark's distribution "
+                "(other seeds)\n" % b["tflops"])
+        if "rule" in b:
+            r = b["rule"]
+            f.write("batch2 %d %d %s %s\n" % (mode, r["threshold"], r["big"], r["small"]))
+            f.write("#   %.1f TFLOP/s on that batch, two concurrent parts\n" % r["tflops"])
+
+
+def merge_table(base_path, out_path, gemm_rows, batch=None):
     """Write base_path to out_path with the entries (and their comment
     lines) of every key in gemm_rows replaced by the new rows, placed where
-    the key's first old entry was (new keys go after the last entry)."""
+    the key's first old entry was (new keys go after the last entry); with
+    `batch` (tune_batch's result), the batch and batch2 lines of its modes
+    are replaced by the new ones, at the end."""
     new = {}
     for r in gemm_rows:
         new.setdefault((r["mode"], r["ta"], r["tb"], r["m"], r["n"], r["k"]), []).append(r)
@@ -242,6 +247,10 @@ def merge_table(base_path, out_path, gemm_rows):
         if line.startswith("#") and skipping:
             continue
         skipping = False
+        if batch and len(parts) >= 3 and parts[0] in ("batch", "batch2") and \
+                int(parts[1]) in batch:
+            skipping = True
+            continue
         if len(parts) == 9 and parts[0] in ("0", "1"):
             key = (int(parts[0]), parts[1], parts[2], int(parts[3]), int(parts[4]), int(parts[5]))
             if key in new:
@@ -260,6 +269,8 @@ def merge_table(base_path, out_path, gemm_rows):
     out[last_entry:last_entry] = rest
     with open(out_path, "w") as f:
         f.writelines(out)
+        if batch:
+            write_batch_lines(f, batch)
 
 
 def main(argv=None):
@@ -273,19 +284,25 @@ def main(argv=None):
                          "rows into the table named by --merge (no batch tuning)")
     ap.add_argument("--rankk", action="store_true",
                     help="with --merge: also tune the 16384^2 x K rank-k keys")
+    ap.add_argument("--batch", action="store_true",
+                    help="with --merge: also retune the batch lines")
     ap.add_argument("--merge", default=None, help="table to merge --sizes rows into")
     args = ap.parse_args(argv)
     os.environ["MISGEMM_TUNING"] = "none"  # tune from the built-in defaults
     from paper_1608_05265_amd import workloads as wl
     keys = default_keys()
-    if args.sizes or args.rankk:
+    if args.sizes or args.rankk or args.batch:
         if not args.merge:
-            ap.error("--sizes and --rankk need --merge")
+            ap.error("--sizes, --rankk and --batch need --merge")
         sizes = {int(v) for v in args.sizes.split(",")} if args.sizes else set()
         keys = [k for k in keys if (k[3] == k[4] == k[5] and k[3] in sizes) or
                 (args.rankk and k[3] == k[4] == 16384 and k[5] in wl.RANKK_KS)]
-        rows = tune_gemm(keys, log=lambda s: print(s, flush=True))
-        merge_table(args.merge, args.out, rows)
+        rows = tune_gemm(keys, log=lambda s: print(s, flush=True)) if keys else []
+        batch = None
+        if args.batch:
+            batch = tune_batch(wl.config5(count=512, seed_case=1),
+                               log=lambda s: print(s, flush=True))
+        merge_table(args.merge, args.out, rows, batch)
         print("wrote", args.out)
         return 0
     if args.quick:

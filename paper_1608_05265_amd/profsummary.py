@@ -36,6 +36,11 @@ import sys
 
 
 def short_name(name: str) -> str:
+    m = re.search(r"misgemm::(\w+)<misgemm::RTileBase<misgemm::RShape<([\d, ]+)>, (\w+), (\w+), "
+                  r"misgemm::RMath(\w+)>", name)
+    if m:
+        shape = "x".join(v.strip() for v in m.group(2).split(","))
+        return "%s<R%s %s %s,%s>" % (m.group(1), m.group(5), shape, m.group(3), m.group(4))
     m = re.search(r"misgemm::(\w+)<misgemm::(\w+)<misgemm::Shape<([\d, ]+)>, ([^>]*)>", name)
     if m:
         shape = "x".join(v.strip() for v in m.group(3).split(","))
