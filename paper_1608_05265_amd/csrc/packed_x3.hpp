@@ -159,7 +159,6 @@ struct X3KTile {
 #pragma unroll
         for (int s = 0; s < PPT; ++s) {
             const int q = tid + s * NT;
-            const __bf16 *src;
             st.v[s] = *reinterpret_cast<const bf16x8 *>(piece(p, m0, n0, kb, q));
         }
     }
