@@ -371,11 +371,15 @@ def tol_d(k: int) -> float:
 
 def tol_false_d(k: int) -> float:
     """Bound for the FP64 interface computed in FP32 (the paper's "false
-    dgemm"): rounding a and b to FP32 perturbs each product by at most
-    (2u + u^2)|a||b|, then the FP32 sum is held to tol(k) of the rounded
-    operands; tol(k) + 2^-22 covers both with room for the second-order terms.
+    dgemm", Section IV-B): rounding a and b to FP32 (RNE, unit roundoff u)
+    perturbs each product by at most (2u + u^2)|a||b|, and the FP32 sum of
+    the rounded products is held to tol(k) times sum |fl(a)||fl(b)|, which
+    is at most (1 + u)^2 sum |a||b|.  So the normalized error is at most
+    tol(k) (1 + u)^2 + 2u + u^2 <= tol(k) (1 + 2^-22) + 2^-23 + 2^-47; the
+    input-rounding term 2u is attained to within a factor 1 - 2^-22 by a
+    one-term product whose factors both round down by almost u (pinned).
     """
-    return tol(k) + 2.0 ** -22
+    return tol(k) * (1.0 + 2.0 ** -22) + 2.0 ** -23 + 2.0 ** -47
 
 
 def normalized_error(C: np.ndarray, cref: np.ndarray, den: np.ndarray):

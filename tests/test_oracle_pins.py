@@ -39,8 +39,28 @@ def test_hpl_residual_formula():
 def test_dgemm_bounds():
     assert oracle.tol_d(4096) == 2 * 4096 * 2.0 ** -53
     assert oracle.tol_d(2) == 5 * 2.0 ** -53
-    # FP32 computation of FP64 data: the FP32 bound plus the input rounding
-    assert oracle.tol_false_d(100) == oracle.tol(100) + 2.0 ** -22
+    # FP32 computation of FP64 data: the FP32 bound (times (1 + u)^2) plus
+    # the input rounding of both factors
+    assert oracle.tol_false_d(100) == oracle.tol(100) * (1 + 2.0 ** -22) + 2.0 ** -23 + 2.0 ** -47
+
+
+def test_false_dgemm_input_rounding_term_is_attained():
+    """The false dgemm bound's input-rounding term (2u + u^2) is attained:
+    a one-term product whose factors 1 + u - 2^-50 both round down to 1 in
+    FP32 has an exact FP32 product, so its whole error is the input
+    rounding, 2u to within a factor 1 - 2^-22 (computed from the definition:
+    FP32 rounding of the inputs, the FP32 product, FP64 comparison).  A
+    derivation that under-counted that term (one factor's rounding, say)
+    would not cover this case."""
+    u = 2.0 ** -24
+    a = b = 1.0 + u - 2.0 ** -50
+    fa, fb = np.float32(a), np.float32(b)
+    assert fa == 1.0 and fb == 1.0                      # both rounded down by almost u
+    c32 = float(np.float32(fa * fb))                    # the FP32 path's product
+    err = abs(c32 - a * b) / (abs(a) * abs(b))          # alpha = 1, beta = 0
+    assert (1 - 2.0 ** -22) * 2 * u <= err <= 2 * u + 2.0 ** -47
+    assert err > u                                      # more than one factor's rounding
+    assert err <= oracle.tol_false_d(1)
 
 
 def test_bf16_rne_matches_torch(o):
