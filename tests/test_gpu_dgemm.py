@@ -1,8 +1,8 @@
 """Double-precision GEMM (the paper's dgemm variants, Section IV-B) against
 the binary128 oracle: FP64 matrix cores within max(2K, K+3) * 2^-53, the
-FP32-compute form ("false dgemm") within tol(K) + 2^-22, every transpose,
-ragged sizes and padded leading dimensions, degenerate cases, exactness on
-integer data, and untouched C padding."""
+FP32-compute form ("false dgemm") within tol(K)(1 + 2^-22) + 2^-23 +
+2^-47, every transpose, ragged sizes and padded leading dimensions,
+degenerate cases, exactness on integer data, and untouched C padding."""
 import numpy as np
 import pytest
 
