@@ -62,7 +62,7 @@ def test_lu_unique_pivots_match_oracle(mode):
     margin, so the GPU pivots equal the oracle's and the factors agree to
     FP32 accuracy; sizes around the leaf widths and with several levels."""
     rng = np.random.default_rng(50)
-    for n in (1, 7, 8, 9, 31, 32, 33, 100, 257):
+    for n in (1, 7, 8, 9, 31, 32, 33, 100, 257, 600, 1100):
         d = rng.uniform(-1, 1, (n, n)) + np.diag(rng.uniform(n, 2 * n, n))
         a = d[rng.permutation(n)].astype(np.float32)
         lu, ipiv, info = _factor(a, mode)[:3]
