@@ -2,7 +2,8 @@
 // tiles than compute units at any staged tile size).
 //
 // A workgroup of KW waves computes a BM x BN tile of 16x16 matrix-core
-// blocks.  K is cut into 64-k chunks; wave w takes chunks w, w + KW, ... and
+// blocks.  K is cut into chunks of 4 KPL k (KPL = 16 or 8: 64 or 32 k);
+// wave w takes chunks w, w + KW, ... and
 // loads each straight from global memory into registers, with no LDS
 // staging and no barrier inside the K loop (the paper's packing step pays
 // off when a panel is reused many times; here every operand element is used
@@ -14,12 +15,13 @@
 //
 // Lane layout of the 16x16 blocks: lane l owns row l % 16 of the op(A)
 // block and column l % 16 of the op(B) block; lane group g = l / 16 holds
-// the 16 consecutive k  c0 + 16g .. c0 + 16g + 15  of chunk c0, so an
-// operand stored k-contiguous is read with four 16-byte loads per lane.
-//   FP32:   v_mfma_f32_16x16x4_f32 step s (0..15) takes k = c0 + 16g + s
+// the KPL consecutive k  c0 + KPL g .. c0 + KPL g + KPL - 1  of chunk c0,
+// so an operand stored k-contiguous is read with KPL/4 16-byte loads per
+// lane.
+//   FP32:   v_mfma_f32_16x16x4_f32 step s (0..KPL-1) takes k = c0 + KPL g + s
 //           from lane group g.
-//   BF16X3: v_mfma_f32_16x16x32_bf16 step t (0, 1) takes the eight
-//           k = c0 + 16g + 8t .. +7 from lane group g; each FP32 element is
+//   BF16X3: v_mfma_f32_16x16x32_bf16 step t (0 .. KPL/8 - 1) takes the eight
+//           k = c0 + KPL g + 8t .. +7 from lane group g; each FP32 element is
 //           split into three bf16 parts in registers and the six part
 //           products of a step are added smallest first into the one FP32
 //           accumulator, as in the staged split-form tiles.
@@ -31,28 +33,32 @@
 
 namespace misgemm {
 
-template <int BM_, int BN_, int KW_>
+// KPL: consecutive k per lane of a chunk (16, or 8 for chunks of 32 k).
+template <int BM_, int BN_, int KW_, int KPL_ = 16>
 struct RShape {
-    static constexpr int BM = BM_, BN = BN_, BK = 64, KW = KW_, OCC = 1;
+    static constexpr int KPL = KPL_;
+    static_assert(KPL == 16 || KPL == 8, "16 or 8 k per lane");
+    static constexpr int BM = BM_, BN = BN_, BK = 4 * KPL, KW = KW_, OCC = 1;
     static constexpr int WM = BM, WN = BN, NWM = 1, NWN = 1, NW = KW, NT = 64 * KW;
     static constexpr int RM = BM / 16, RN = BN / 16;  // 16x16 blocks
     static_assert(BM % 16 == 0 && BN % 16 == 0, "the tile is made of 16x16 blocks");
 };
 
-// The 16 values  op(X)(row, k0 + s), s = 0..15,  of one row of op(X) (rows x
-// kdim).  KC: op(X)(r, k) = X[k + r*ld] (k contiguous), else X[r + k*ld].
-// FAST: row < rows and k0 + 16 <= kdim hold, and for KC the 16-byte loads are
-// aligned (base 16-byte aligned, ld % 4 == 0; k0 is a multiple of 16).
-// Otherwise entries outside op(X) read as zero and are not loaded.
-template <bool FAST, bool KC>
-__device__ __forceinline__ void rload16(const float *__restrict__ X, int64_t ld, int64_t row,
-                                        int64_t k0, int64_t rows, int64_t kdim, float (&v)[16])
+// The N values  op(X)(row, k0 + s), s = 0..N-1 (N = 16 or 8), of one row
+// of op(X) (rows x kdim).  KC: op(X)(r, k) = X[k + r*ld] (k contiguous),
+// else X[r + k*ld].  FAST: row < rows and k0 + N <= kdim hold, and for KC
+// the 16-byte loads are aligned (base 16-byte aligned, ld % 4 == 0; k0 is
+// a multiple of N).  Otherwise entries outside op(X) read as zero and are
+// not loaded.
+template <bool FAST, bool KC, int N>
+__device__ __forceinline__ void rload(const float *__restrict__ X, int64_t ld, int64_t row,
+                                      int64_t k0, int64_t rows, int64_t kdim, float (&v)[N])
 {
     if constexpr (KC) {
         const float *p = X + row * ld + k0;
         if constexpr (FAST) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < N / 4; ++q) {
                 const floatx4 t = *reinterpret_cast<const floatx4 *>(p + 4 * q);
 #pragma unroll
                 for (int e = 0; e < 4; ++e) v[4 * q + e] = t[e];
@@ -60,17 +66,17 @@ __device__ __forceinline__ void rload16(const float *__restrict__ X, int64_t ld,
         } else {
             const bool rok = row < rows;
 #pragma unroll
-            for (int s = 0; s < 16; ++s) v[s] = (rok && k0 + s < kdim) ? p[s] : 0.0f;
+            for (int s = 0; s < N; ++s) v[s] = (rok && k0 + s < kdim) ? p[s] : 0.0f;
         }
     } else {
         const float *p = X + row + k0 * ld;
         if constexpr (FAST) {
 #pragma unroll
-            for (int s = 0; s < 16; ++s) v[s] = p[s * ld];
+            for (int s = 0; s < N; ++s) v[s] = p[s * ld];
         } else {
             const bool rok = row < rows;
 #pragma unroll
-            for (int s = 0; s < 16; ++s) v[s] = (rok && k0 + s < kdim) ? p[s * ld] : 0.0f;
+            for (int s = 0; s < N; ++s) v[s] = (rok && k0 + s < kdim) ? p[s * ld] : 0.0f;
         }
     }
 }
@@ -150,7 +156,7 @@ __device__ __forceinline__ void repilogue(const GemmArgs &g, const floatx4 (&acc
 // matrix-core work of one chunk.
 template <class SH, bool TA, bool TB, class MATH>
 struct RTileBase {
-    static constexpr int KW = SH::KW, RM = SH::RM, RN = SH::RN, NT = SH::NT;
+    static constexpr int KW = SH::KW, RM = SH::RM, RN = SH::RN, NT = SH::NT, KPL = SH::KPL;
     static constexpr int LDS_BYTES = (KW > 1 ? (KW - 1) : 1) * RM * RN * 4 * 64 * 4;
 
     template <bool SPLIT = false>
@@ -167,15 +173,15 @@ struct RTileBase {
 
     template <bool FAST>
     __device__ __forceinline__ static void load(const GemmArgs &g, int64_t m0, int64_t n0,
-                                                int64_t k0, int r, float (&a)[RM][16],
-                                                float (&b)[RN][16])
+                                                int64_t k0, int r, float (&a)[RM][KPL],
+                                                float (&b)[RN][KPL])
     {
 #pragma unroll
         for (int i = 0; i < RM; ++i)
-            rload16<FAST, TA>(g.A, g.lda, m0 + i * 16 + r, k0, g.m, g.k, a[i]);
+            rload<FAST, TA, KPL>(g.A, g.lda, m0 + i * 16 + r, k0, g.m, g.k, a[i]);
 #pragma unroll
         for (int j = 0; j < RN; ++j)
-            rload16<FAST, !TB>(g.B, g.ldb, n0 + j * 16 + r, k0, g.n, g.k, b[j]);
+            rload<FAST, !TB, KPL>(g.B, g.ldb, n0 + j * 16 + r, k0, g.n, g.k, b[j]);
     }
 
     template <bool FAST>
@@ -192,23 +198,23 @@ struct RTileBase {
 #pragma unroll
                 for (int e = 0; e < 4; ++e) acc[i][j][e] = 0.0f;
         const int64_t chunks = (g.k + SH::BK - 1) / SH::BK;
-        float a[RM][16], b[RN][16];
+        float a[RM][KPL], b[RN][KPL];
         int64_t c = wave;
-        if (c < chunks) load<FAST>(g, m0, n0, c * SH::BK + 16 * grp, r, a, b);
+        if (c < chunks) load<FAST>(g, m0, n0, c * SH::BK + KPL * grp, r, a, b);
         while (c < chunks) {
             const int64_t cn = c + KW;
-            float a2[RM][16], b2[RN][16];
-            if (cn < chunks) load<FAST>(g, m0, n0, cn * SH::BK + 16 * grp, r, a2, b2);
-            MATH::template step<RM, RN>(a, b, acc);
+            float a2[RM][KPL], b2[RN][KPL];
+            if (cn < chunks) load<FAST>(g, m0, n0, cn * SH::BK + KPL * grp, r, a2, b2);
+            MATH::template step<RM, RN, KPL>(a, b, acc);
             if (cn < chunks) {
 #pragma unroll
                 for (int i = 0; i < RM; ++i)
 #pragma unroll
-                    for (int s = 0; s < 16; ++s) a[i][s] = a2[i][s];
+                    for (int s = 0; s < KPL; ++s) a[i][s] = a2[i][s];
 #pragma unroll
                 for (int j = 0; j < RN; ++j)
 #pragma unroll
-                    for (int s = 0; s < 16; ++s) b[j][s] = b2[j][s];
+                    for (int s = 0; s < KPL; ++s) b[j][s] = b2[j][s];
             }
             c = cn;
         }
@@ -218,12 +224,12 @@ struct RTileBase {
 };
 
 struct RMathF32 {
-    template <int RM, int RN>
-    __device__ __forceinline__ static void step(const float (&a)[RM][16], const float (&b)[RN][16],
-                                                floatx4 (&acc)[RM][RN])
+    template <int RM, int RN, int KPL>
+    __device__ __forceinline__ static void step(const float (&a)[RM][KPL],
+                                                const float (&b)[RN][KPL], floatx4 (&acc)[RM][RN])
     {
 #pragma unroll
-        for (int s = 0; s < 16; ++s)
+        for (int s = 0; s < KPL; ++s)
 #pragma unroll
             for (int i = 0; i < RM; ++i)
 #pragma unroll
@@ -234,12 +240,12 @@ struct RMathF32 {
 };
 
 struct RMathX3 {
-    template <int RM, int RN>
-    __device__ __forceinline__ static void step(const float (&a)[RM][16], const float (&b)[RN][16],
-                                                floatx4 (&acc)[RM][RN])
+    template <int RM, int RN, int KPL>
+    __device__ __forceinline__ static void step(const float (&a)[RM][KPL],
+                                                const float (&b)[RN][KPL], floatx4 (&acc)[RM][RN])
     {
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
+        for (int t = 0; t < KPL / 8; ++t) {
             bf16x8 ap[RM][3], bp[RN][3];
 #pragma unroll
             for (int i = 0; i < RM; ++i)

@@ -74,6 +74,8 @@ void register_f32(std::vector<ConfigEntry> &out)
     // register tiles: four waves take 64-k chunks in turn
     out.push_back(make_f32<F32R, RShape<16, 16, 4>, false>("fp32r_16x16x64_r4"));
     out.push_back(make_f32<F32R, RShape<32, 32, 4>, true>("fp32r_32x32x64_r4"));
+    // eight waves taking 32-k chunks in turn (half the loads per wave)
+    out.push_back(make_f32<F32R, RShape<16, 16, 8, 8>, false>("fp32r_16x16x32_r8"));
 }
 
 }  // namespace misgemm
