@@ -18,6 +18,7 @@
 // interchanges run in LDS and the triangular recursion stops at 1024-row
 // diagonal blocks that one workgroup solves.
 #include <hip/hip_runtime.h>
+#include <float.h>
 #include <stdint.h>
 
 #include "../../include/misgemm.h"
@@ -91,16 +92,28 @@ __device__ inline uint64_t wave_max_key(uint64_t k)
                   umax64(readlane64(k, 32), readlane64(k, 48)));
 }
 
+// The multipliers of a pivot column: the entries below the pivot times the
+// pivot's reciprocal when the pivot is at least the smallest normal number
+// (so that the reciprocal is finite), as LAPACK's sgetf2 and HPL scale the
+// column, else divided by the pivot.
+__device__ inline bool scale_by_reciprocal(float piv) { return fabsf(piv) >= FLT_MIN; }
+
 // Factor the m x w panel P (w <= W, m <= RPT * LEAF_THREADS, leading
 // dimension lda; its top-left element is A(row0, row0)).  Thread t holds
-// rows t, t + LEAF_THREADS, ... of the panel in registers.  For each column
-// j: the row of largest magnitude at or below j (first one on ties) is
-// exchanged with row j across the panel, the column below the diagonal is
-// divided by the pivot, and the outer product is subtracted from the
-// remaining columns.  A zero pivot leaves its column as it is and records
-// row0 + j + 1 in *info if no earlier zero pivot did.  ipiv receives
-// global row indices.  Two barriers per column: one after the per-wave
-// maxima are posted, one after the two exchanged rows are posted.
+// rows t, t + LEAF_THREADS, ... of the panel in registers; the rows past m
+// hold NaN, so that they are never a pivot candidate and need no mask (they
+// are not stored).  For each column j: the row of largest magnitude at or
+// below j (first one on ties) is exchanged with row j across the panel,
+// the entries below the diagonal become multipliers, and the outer product
+// is subtracted from the remaining columns.  A zero pivot leaves its column
+// as it is and records row0 + j + 1 in *info if no earlier zero pivot did.
+// ipiv receives global row indices.  One barrier per column: before it,
+// every wave posts its own candidate row (its largest key) and folds the
+// key into an LDS maximum, and thread j posts row j; after it, every thread
+// reads the winning key and takes the pivot row from the wave that owns it.
+// The row buffers alternate between even and odd columns and the maximum
+// cycles over three slots (one is cleared two columns ahead of its use), so
+// a wave that runs ahead never overwrites what a slower one still reads.
 template <int RPT, int W, bool UPD>
 __global__ __launch_bounds__(LEAF_THREADS) void lu_leaf_kernel(float *__restrict__ P,
                                                               int64_t lda, int m, int w, int wl,
@@ -108,11 +121,14 @@ __global__ __launch_bounds__(LEAF_THREADS) void lu_leaf_kernel(float *__restrict
                                                               int64_t row0, int *__restrict__ info)
 {
     static_assert(RPT * W <= LEAF_REGS, "panel does not fit the register budget");
-    static_assert(LEAF_WAVES <= 16, "per-wave maxima are combined in one 16-lane row");
-    __shared__ uint64_t wkey[LEAF_WAVES];
-    __shared__ float prow[W], jrow[W];
+    static_assert(LEAF_THREADS % 64 == 0, "waves own whole 64-row groups of a thread row");
+    __shared__ float wrow[2][LEAF_WAVES][W];   // each wave's candidate row
+    __shared__ float jrow[2][W];               // row j before its exchange
+    __shared__ unsigned long long gkey[3];     // largest pivot key of the column
     __shared__ float su[W][W];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const float qnan = __int_as_float(0x7fc00000);
+    if (t < 3) gkey[t] = 0;
     float v[RPT][W];
 #pragma unroll
     for (int c = 0; c < W; ++c) {
@@ -120,9 +136,10 @@ __global__ __launch_bounds__(LEAF_THREADS) void lu_leaf_kernel(float *__restrict
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
             const uint32_t r = (uint32_t)(t + i * LEAF_THREADS);
-            v[i][c] = (r < (uint32_t)m && c < w) ? pc[r] : 0.0f;
+            v[i][c] = r < (uint32_t)m ? (c < w ? pc[r] : 0.0f) : qnan;
         }
     }
+    __syncthreads();  // gkey cleared
     if (UPD && wl > 0) {
         // The parent node's update from the left sibling leaf (the wl <= W
         // columns left of the panel, already factored and swapped): U12 = L11^{-1}
@@ -167,65 +184,87 @@ __global__ __launch_bounds__(LEAF_THREADS) void lu_leaf_kernel(float *__restrict
 #pragma unroll
     for (int j = 0; j < W; ++j) {
         if (j >= w) break;
-        uint64_t key = 0;
+        const int b2 = j & 1, b3 = j % 3;
+        // this thread's candidate: its first row at or below j of largest
+        // magnitude (NaN never compares greater, rows above j take -1)
+        float best = -1.0f;
+        int bi = 0;
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
-            const int r = t + i * LEAF_THREADS;
-            const float a = fabsf(v[i][j]);
-            const bool cand = r >= j && r < m && !__builtin_isnan(a);
-            key = umax64(key, cand ? pivot_key(a, r) : 0);
+            const float a = (i == 0 && t < j) ? -1.0f : fabsf(v[i][j]);
+            if (a > best) {
+                best = a;
+                bi = i;
+            }
         }
-        key = wave_max_key(key);
-        if (lane == 0) wkey[wave] = key;
+        const uint64_t key = wave_max_key(best >= 0.0f ? pivot_key(best, t + bi * LEAF_THREADS) : 0);
+        if (key != 0) {  // uniform
+            const int r = (int)(0xFFFFFFFFu - (uint32_t)key);
+            if (lane == (r & 63)) {
+                const int ri = r / LEAF_THREADS;
+#pragma unroll
+                for (int i = 0; i < RPT; ++i)
+                    if (i == ri) {
+#pragma unroll
+                        for (int c = 0; c < W; ++c) wrow[b2][wave][c] = v[i][c];
+                    }
+                atomicMax(&gkey[b3], (unsigned long long)key);
+            }
+        }
+        if (t == j) {
+#pragma unroll
+            for (int c = 0; c < W; ++c) jrow[b2][c] = v[0][c];
+        }
         __syncthreads();
-        key = row_max_key(lane < LEAF_WAVES ? wkey[lane] : 0);
-        key = readlane64(key, 0);
-        const int idx = key == 0 ? -1 : (int)(0xFFFFFFFFu - (uint32_t)key);
-        const float pivot_mag = key == 0 ? -1.0f : __uint_as_float((uint32_t)(key >> 32));
+        const uint64_t g0 = gkey[b3];
+        const uint64_t g = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(g0 >> 32)) << 32) |
+                           (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)g0);
+        if (t == 0) gkey[(j + 2) % 3] = 0;  // last read before this column's barrier
+        const int idx = g == 0 ? -1 : (int)(0xFFFFFFFFu - (uint32_t)g);
+        const float pivot_mag = g == 0 ? -1.0f : __uint_as_float((uint32_t)(g >> 32));
         const int p = idx >= 0 ? idx : j;
         const int pt = p % LEAF_THREADS, pi = p / LEAF_THREADS;
         if (t == 0) ipiv[row0 + j] = row0 + p;
-        // post the pivot row (the new row j) and, when it moves, row j
-        if (t == pt) {
+        // the pivot row, the new row j (row j itself when nothing qualifies)
+        float u[W];
 #pragma unroll
-            for (int i = 0; i < RPT; ++i)
-                if (i == pi) {
-#pragma unroll
-                    for (int c = 0; c < W; ++c) prow[c] = v[i][c];
-                }
-        }
-        if (t == j && p != j) {
-#pragma unroll
-            for (int c = 0; c < W; ++c) jrow[c] = v[0][c];
-        }
-        __syncthreads();
+        for (int c = 0; c < W; ++c) u[c] = g != 0 ? wrow[b2][pt >> 6][c] : jrow[b2][c];
         if (p != j) {
             if (t == j) {
 #pragma unroll
-                for (int c = 0; c < W; ++c) v[0][c] = prow[c];
+                for (int c = 0; c < W; ++c) v[0][c] = u[c];
             }
             if (t == pt) {
 #pragma unroll
                 for (int i = 0; i < RPT; ++i)
                     if (i == pi) {
 #pragma unroll
-                        for (int c = 0; c < W; ++c) v[i][c] = jrow[c];
+                        for (int c = 0; c < W; ++c) v[i][c] = jrow[b2][c];
                     }
             }
         }
-        const float piv = prow[j];
+        const float piv = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(u[j])));
         if (pivot_mag > 0.0f && piv != 0.0f) {
-            float u[W];
+            float l[RPT];
+            if (scale_by_reciprocal(piv)) {
+                const float rinv = 1.0f / piv;
 #pragma unroll
-            for (int c = j + 1; c < W; ++c) u[c] = prow[c];
+                for (int i = 0; i < RPT; ++i) l[i] = v[i][j] * rinv;
+            } else {
 #pragma unroll
-            for (int i = 0; i < RPT; ++i) {
-                const int r = t + i * LEAF_THREADS;
-                const bool below = r > j && r < m;
-                const float l = v[i][j] / piv;
-                v[i][j] = below ? l : v[i][j];
+                for (int i = 0; i < RPT; ++i) l[i] = v[i][j] / piv;
+            }
+            // the thread's first row is the only one that can lie at or
+            // above row j (rows i >= 1 are LEAF_THREADS or more further down)
+            const bool below = t > j;
+            v[0][j] = below ? l[0] : v[0][j];
 #pragma unroll
-                for (int c = j + 1; c < W; ++c) v[i][c] = below ? v[i][c] - l * u[c] : v[i][c];
+            for (int c = j + 1; c < W; ++c) v[0][c] = below ? v[0][c] - l[0] * u[c] : v[0][c];
+#pragma unroll
+            for (int i = 1; i < RPT; ++i) {
+                v[i][j] = l[i];
+#pragma unroll
+                for (int c = j + 1; c < W; ++c) v[i][c] -= l[i] * u[c];
             }
         } else if (t == 0 && *info == 0) {
             *info = (int)(row0 + j + 1);
@@ -289,7 +328,12 @@ __global__ __launch_bounds__(LEAF_THREADS) void lu_leaf_tall_kernel(float *__res
         __syncthreads();
         const float piv = col[j];
         if (pivot_mag > 0.0f && piv != 0.0f) {
-            for (int64_t r = j + 1 + t; r < m; r += LEAF_THREADS) col[r] = col[r] / piv;
+            if (scale_by_reciprocal(piv)) {
+                const float rinv = 1.0f / piv;
+                for (int64_t r = j + 1 + t; r < m; r += LEAF_THREADS) col[r] = col[r] * rinv;
+            } else {
+                for (int64_t r = j + 1 + t; r < m; r += LEAF_THREADS) col[r] = col[r] / piv;
+            }
             if (t > j && t < w) urow[t] = P[j + (int64_t)t * lda];
             __syncthreads();
             for (int64_t r = j + 1 + t; r < m; r += LEAF_THREADS) {
