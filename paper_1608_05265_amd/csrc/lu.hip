@@ -13,7 +13,9 @@
 // it, which gives the same result as swapping at each level of the
 // recursion (a column receives the interchanges in pivot order either way,
 // and the columns right of a range are not touched before its left half is
-// done).  The solve applies the interchanges to the right-hand sides and
+// done); for a node whose halves are both leaves, the right leaf first
+// takes the left one's interchanges on its own columns and one launch after
+// the pair applies both leaves' to every other column.  The solve applies the interchanges to the right-hand sides and
 // then the two triangular solves; with few right-hand sides the
 // interchanges run in LDS and the triangular recursion stops at 1024-row
 // diagonal blocks that one workgroup solves.
@@ -92,6 +94,10 @@ __device__ inline uint64_t wave_max_key(uint64_t k)
                   umax64(readlane64(k, 32), readlane64(k, 48)));
 }
 
+__device__ inline void laswp_wave(float *__restrict__ C, int64_t ldc, int64_t nrows, int64_t ncols,
+                                  int64_t gap0, int64_t gapw, const int64_t *__restrict__ ipiv,
+                                  int64_t k0, int64_t k1, int64_t cbase, int t);
+
 // The multipliers of a pivot column: the entries below the pivot times the
 // pivot's reciprocal when the pivot is at least the smallest normal number
 // (so that the reciprocal is finite), as LAPACK's sgetf2 and HPL scale the
@@ -107,7 +113,12 @@ __device__ inline bool scale_by_reciprocal(float piv) { return fabsf(piv) >= FLT
 // the entries below the diagonal become multipliers, and the outer product
 // is subtracted from the remaining columns.  A zero pivot leaves its column
 // as it is and records row0 + j + 1 in *info if no earlier zero pivot did.
-// ipiv receives global row indices.  One barrier per column: before it,
+// ipiv receives global row indices.  With UPD and wl > 0 the panel is the
+// right half of a node whose left half (the wl columns left of it) is the
+// leaf just factored: wavefront 0 first applies that leaf's interchanges
+// (rows row0 - wl .. row0 - 1 with their pivot rows) to the panel's columns
+// over the whole matrix height, then the node's solve and update run on the
+// panel (below).  One barrier per column: before it,
 // every wave posts its own candidate row (its largest key) and folds the
 // key into an LDS maximum, and thread j posts row j; after it, every thread
 // reads the winning key and takes the pivot row from the wave that owns it.
@@ -129,6 +140,12 @@ __global__ __launch_bounds__(LEAF_THREADS) void lu_leaf_kernel(float *__restrict
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const float qnan = __int_as_float(0x7fc00000);
     if (t < 3) gkey[t] = 0;
+    if (UPD && wl > 0) {
+        // the left sibling's interchanges on this panel's columns (global row
+        // 0 of the panel's first column is P - row0)
+        if (wave == 0) laswp_wave(P - row0, lda, row0 + m, w, w, 0, ipiv, row0 - wl, row0, 0, lane);
+        __syncthreads();
+    }
     float v[RPT][W];
 #pragma unroll
     for (int c = 0; c < W; ++c) {
@@ -387,16 +404,12 @@ __device__ inline void laswp_move(float *__restrict__ C, int64_t ldc, int64_t nc
     }
 }
 
-__global__ __launch_bounds__(SWAP_THREADS) void laswp_kernel(float *__restrict__ C, int64_t ldc,
-                                                            int64_t nrows, int64_t ncols,
-                                                            int64_t gap0, int64_t gapw,
-                                                            const int64_t *__restrict__ ipiv,
-                                                            int64_t k0, int64_t k1)
+// One wavefront's share of the interchanges: columns cbase ..
+// cbase + SWAP_COLS_PER_WAVE - 1 (those below ncols) of C, lane t.
+__device__ inline void laswp_wave(float *__restrict__ C, int64_t ldc, int64_t nrows, int64_t ncols,
+                                  int64_t gap0, int64_t gapw, const int64_t *__restrict__ ipiv,
+                                  int64_t k0, int64_t k1, int64_t cbase, int t)
 {
-    const int t = threadIdx.x & 63;
-    const int64_t cbase =
-        ((int64_t)blockIdx.x * (SWAP_THREADS / 64) + (threadIdx.x >> 6)) * SWAP_COLS_PER_WAVE;
-    if (cbase >= ncols) return;  // whole wavefront past the last column
     for (int64_t kb = k0; kb < k1; kb += SWAP_BLOCK) {
         const int nb = (int)(k1 - kb < SWAP_BLOCK ? k1 - kb : SWAP_BLOCK);
         int64_t p = -1;
@@ -432,6 +445,27 @@ __global__ __launch_bounds__(SWAP_THREADS) void laswp_kernel(float *__restrict__
             laswp_move<32>(C, ldc, ncols, gap0, gapw, cbase, t, row, content);
         else
             laswp_move<64>(C, ldc, ncols, gap0, gapw, cbase, t, row, content);
+    }
+}
+
+// The interchanges on the columns of the first main_blocks workgroups
+// (laswp_wave's arguments); the workgroups after them take the band of
+// bandw columns at band0, with the interchanges bk0 .. k1-1 only.
+__global__ __launch_bounds__(SWAP_THREADS) void laswp_kernel(
+    float *__restrict__ C, int64_t ldc, int64_t nrows, int64_t ncols, int64_t gap0, int64_t gapw,
+    const int64_t *__restrict__ ipiv, int64_t k0, int64_t k1, int64_t main_blocks, int64_t band0,
+    int64_t bandw, int64_t bk0)
+{
+    const int t = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if ((int64_t)blockIdx.x < main_blocks) {
+        const int64_t cbase = ((int64_t)blockIdx.x * (SWAP_THREADS / 64) + wave) * SWAP_COLS_PER_WAVE;
+        if (cbase >= ncols) return;  // whole wavefront past the last column
+        laswp_wave(C, ldc, nrows, ncols, gap0, gapw, ipiv, k0, k1, cbase, t);
+    } else {
+        const int64_t cbase =
+            (((int64_t)blockIdx.x - main_blocks) * (SWAP_THREADS / 64) + wave) * SWAP_COLS_PER_WAVE;
+        if (cbase >= bandw) return;
+        laswp_wave(C + band0 * ldc, ldc, nrows, bandw, bandw, 0, ipiv, bk0, k1, cbase, t);
     }
 }
 
@@ -596,15 +630,18 @@ int gemm(const Lu &c, int64_t m, int64_t n, int64_t k, const float *A, int64_t l
 }
 
 // Interchanges k0..k1-1 on ncols columns of C (all rows of the matrix),
-// skipping the band of gapw columns at gap0.
+// skipping the band of gapw columns at gap0; with bandw > 0 the same launch
+// also applies the interchanges bk0..k1-1 to the bandw columns at band0.
 int laswp(const Lu &c, float *C, int64_t ldc, int64_t ncols, int64_t gap0, int64_t gapw,
-          int64_t k0, int64_t k1)
+          int64_t k0, int64_t k1, int64_t band0 = 0, int64_t bandw = 0, int64_t bk0 = 0)
 {
-    if (ncols <= 0 || k1 <= k0) return 0;
     constexpr int cols_per_block = SWAP_THREADS / 64 * SWAP_COLS_PER_WAVE;
-    hipLaunchKernelGGL(laswp_kernel, dim3((unsigned)((ncols + cols_per_block - 1) / cols_per_block)),
+    const int64_t main_blocks = k1 > k0 ? (ncols + cols_per_block - 1) / cols_per_block : 0;
+    const int64_t band_blocks = k1 > bk0 ? (bandw + cols_per_block - 1) / cols_per_block : 0;
+    if (main_blocks + band_blocks <= 0) return 0;
+    hipLaunchKernelGGL(laswp_kernel, dim3((unsigned)(main_blocks + band_blocks)),
                        dim3(SWAP_THREADS), 0, c.s, C, ldc, c.n, ncols, gap0, gapw, c.ipiv, k0,
-                       k1);
+                       k1, main_blocks, band0, bandw, bk0);
     return check(hipGetLastError());
 }
 
@@ -733,12 +770,14 @@ int getrf(const Lu &c, int64_t j0, int64_t w)
     const int rpt2 = leaf_rpt(m2);
     if (w <= 2 * lw && rpt2 > 0 && rpt2 <= LEAF_UPD_RPT && w1 <= leaf_width(m2) &&
         w2 <= leaf_width(m2)) {
-        // both halves are leaves: the right one applies this node's solve and
-        // update itself (no separate triangular-solve and sgemm launches)
+        // both halves are leaves: the right one applies the left one's
+        // interchanges to its own columns and this node's solve and update
+        // itself (no separate interchange, triangular-solve and sgemm
+        // launches); then one launch takes the node's interchanges to every
+        // column outside it and the right half's to the left half
         if ((rc = leaf(c, P, m, (int)w1, j0, 0))) return rc;
-        if ((rc = laswp(c, c.A, c.lda, c.n - w1, j0, w1, j0, j0 + w1))) return rc;
         if ((rc = leaf(c, P + w1 + w1 * c.lda, m2, (int)w2, j0 + w1, (int)w1))) return rc;
-        return laswp(c, c.A, c.lda, c.n - w2, j0 + w1, w2, j0 + w1, j0 + w);
+        return laswp(c, c.A, c.lda, c.n - w, j0, w, j0, j0 + w, j0, w1, j0 + w1);
     }
     if ((rc = getrf(c, j0, w1))) return rc;
     if ((rc = trsm(c, false, P, c.lda, P + w1 * c.lda, c.lda, w1, w2))) return rc;
