@@ -417,9 +417,11 @@ __device__ inline void laswp_wave(float *__restrict__ C, int64_t ldc, int64_t nr
             p = ipiv[kb + t];
             if (p < 0 || p >= nrows) p = kb + t;
         }
+        // the composition reads uniform lanes: scalar readlanes, not the
+        // LDS-routed lane shuffles (it is the dependent chain of a launch)
         int first = t;
         for (int i = 0; i < nb; ++i) {
-            const int64_t q = __shfl(p, i);
+            const int64_t q = (int64_t)readlane64((uint64_t)p, i);
             if (i < t && q == p && first == t) first = i;
         }
         int pslot = -1;
@@ -434,8 +436,9 @@ __device__ inline void laswp_wave(float *__restrict__ C, int64_t ldc, int64_t nr
         // compose: content = slot whose original value ends in slot t
         int content = t;
         for (int i = 0; i < nb; ++i) {
-            const int b = __shfl(pslot, i);
-            const int ca = __shfl(content, i), cb = __shfl(content, b);
+            const int b = __builtin_amdgcn_readlane(pslot, i);
+            const int ca = __builtin_amdgcn_readlane(content, i);
+            const int cb = __builtin_amdgcn_readlane(content, b);
             if (t == i) content = cb;
             else if (t == b) content = ca;
         }
