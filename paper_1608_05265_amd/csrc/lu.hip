@@ -519,12 +519,30 @@ __device__ inline float lane_value(float x, int q)
 // the wavefront holds one column).  The lower solve takes
 // the terms of x_i in the order k = 0, 1, ..., i-1; the upper one in the
 // order k = n-1, ..., i+1, then divides by the diagonal.
-template <bool UPPER, int N>
+// With SWAP the workgroup first applies the interchanges k0..k1-1 to its
+// columns of B over the whole matrix height (B's row 0 is matrix row row0;
+// nrows rows in all), one wavefront per SWAP_COLS_PER_WAVE columns, then
+// solves: the left sibling leaf's interchanges on the right half's columns,
+// where the node's halves are leaves too tall to fuse its update.
+template <bool UPPER, int N, bool SWAP>
 __global__ __launch_bounds__(256) void trsm_leaf_kernel(const float *__restrict__ T, int64_t ldt,
                                                        float *__restrict__ B, int64_t ldb, int n,
-                                                       int64_t ncols)
+                                                       int64_t ncols,
+                                                       const int64_t *__restrict__ ipiv,
+                                                       int64_t nrows, int64_t row0, int64_t k0,
+                                                       int64_t k1)
 {
     constexpr int CPW = 64 / N;
+    if (SWAP) {
+        constexpr int CPB = 4 * CPW;  // columns of a workgroup
+        const int64_t c0 = (int64_t)blockIdx.x * CPB;
+        const int64_t bc = ncols - c0 < CPB ? ncols - c0 : CPB;
+        const int64_t cb = (int64_t)(threadIdx.x >> 6) * SWAP_COLS_PER_WAVE;
+        if (cb < bc)  // wavefront-uniform
+            laswp_wave(B - row0 + c0 * ldb, ldb, nrows, bc, bc, 0, ipiv, k0, k1, cb,
+                       threadIdx.x & 63);
+        __syncthreads();
+    }
     const int lane = threadIdx.x & 63, i = lane % N, g = lane / N;
     const int64_t c = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * CPW + g;
     const bool act = c < ncols && i < n;
@@ -648,28 +666,34 @@ int laswp(const Lu &c, float *C, int64_t ldc, int64_t ncols, int64_t gap0, int64
     return check(hipGetLastError());
 }
 
+// k1 > k0: the interchanges k0..k1-1 go to B's columns first (B's row 0 is
+// matrix row row0).
 template <bool UPPER, int N>
 void launch_trsm_leaf_n(const Lu &c, const float *T, int64_t ldt, float *B, int64_t ldb, int n,
-                        int64_t ncols)
+                        int64_t ncols, int64_t row0, int64_t k0, int64_t k1)
 {
     constexpr int cols_per_block = 4 * (64 / N);
-    hipLaunchKernelGGL((trsm_leaf_kernel<UPPER, N>),
-                       dim3((unsigned)((ncols + cols_per_block - 1) / cols_per_block)), dim3(256),
-                       0, c.s, T, ldt, B, ldb, n, ncols);
+    const dim3 grid((unsigned)((ncols + cols_per_block - 1) / cols_per_block)), block(256);
+    if (k1 > k0)
+        hipLaunchKernelGGL((trsm_leaf_kernel<UPPER, N, true>), grid, block, 0, c.s, T, ldt, B,
+                           ldb, n, ncols, c.ipiv, c.n, row0, k0, k1);
+    else
+        hipLaunchKernelGGL((trsm_leaf_kernel<UPPER, N, false>), grid, block, 0, c.s, T, ldt, B,
+                           ldb, n, ncols, c.ipiv, c.n, row0, k0, k1);
 }
 
 template <bool UPPER>
 void launch_trsm_leaf(const Lu &c, const float *T, int64_t ldt, float *B, int64_t ldb, int n,
-                      int64_t ncols)
+                      int64_t ncols, int64_t row0 = 0, int64_t k0 = 0, int64_t k1 = 0)
 {
     if (n <= 8)
-        launch_trsm_leaf_n<UPPER, 8>(c, T, ldt, B, ldb, n, ncols);
+        launch_trsm_leaf_n<UPPER, 8>(c, T, ldt, B, ldb, n, ncols, row0, k0, k1);
     else if (n <= 16)
-        launch_trsm_leaf_n<UPPER, 16>(c, T, ldt, B, ldb, n, ncols);
+        launch_trsm_leaf_n<UPPER, 16>(c, T, ldt, B, ldb, n, ncols, row0, k0, k1);
     else if (n <= 32)
-        launch_trsm_leaf_n<UPPER, 32>(c, T, ldt, B, ldb, n, ncols);
+        launch_trsm_leaf_n<UPPER, 32>(c, T, ldt, B, ldb, n, ncols, row0, k0, k1);
     else
-        launch_trsm_leaf_n<UPPER, LEAF>(c, T, ldt, B, ldb, n, ncols);
+        launch_trsm_leaf_n<UPPER, LEAF>(c, T, ldt, B, ldb, n, ncols, row0, k0, k1);
 }
 
 template <bool UPPER>
@@ -780,6 +804,22 @@ int getrf(const Lu &c, int64_t j0, int64_t w)
         // column outside it and the right half's to the left half
         if ((rc = leaf(c, P, m, (int)w1, j0, 0))) return rc;
         if ((rc = leaf(c, P + w1 + w1 * c.lda, m2, (int)w2, j0 + w1, (int)w1))) return rc;
+        return laswp(c, c.A, c.lda, c.n - w, j0, w, j0, j0 + w, j0, w1, j0 + w1);
+    }
+    if (w1 <= lw && w2 <= leaf_width(m2) && w1 <= LEAF) {
+        // both halves are leaves, too tall for the right one to take the
+        // node's update: the triangular solve applies the left leaf's
+        // interchanges to the right half's columns before solving, and one
+        // launch after the pair takes the node's interchanges to every
+        // other column and the right leaf's to the left one (as above)
+        if ((rc = leaf(c, P, m, (int)w1, j0, 0))) return rc;
+        launch_trsm_leaf<false>(c, P, c.lda, P + w1 * c.lda, c.lda, (int)w1, w2, j0, j0,
+                                j0 + w1);
+        if ((rc = check(hipGetLastError()))) return rc;
+        if ((rc = gemm(c, m - w1, w2, w1, P + w1, c.lda, P + w1 * c.lda, c.lda,
+                       P + w1 + w1 * c.lda, c.lda)))
+            return rc;
+        if ((rc = leaf(c, P + w1 + w1 * c.lda, m2, (int)w2, j0 + w1, 0))) return rc;
         return laswp(c, c.A, c.lda, c.n - w, j0, w, j0, j0 + w, j0, w1, j0 + w1);
     }
     if ((rc = getrf(c, j0, w1))) return rc;
