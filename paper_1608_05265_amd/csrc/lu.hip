@@ -13,10 +13,12 @@
 // it, which gives the same result as swapping at each level of the
 // recursion (a column receives the interchanges in pivot order either way,
 // and the columns right of a range are not touched before its left half is
-// done); for a node whose halves are both leaves, the right leaf first
-// takes the left one's interchanges on its own columns and one launch after
-// the pair applies both leaves' to every other column.  The solve applies the interchanges to the right-hand sides and
-// then the two triangular solves; with few right-hand sides the
+// done); for a node whose halves are both leaves, the right leaf (or, for
+// leaves too tall to take the node's update, the node's triangular-solve
+// leaf) first applies the left one's interchanges to the right half's
+// columns, and one launch after the pair applies both leaves' to every
+// other column.  The solve applies the interchanges to the right-hand
+// sides and then the two triangular solves; with few right-hand sides the
 // interchanges run in LDS and the triangular recursion stops at 1024-row
 // diagonal blocks that one workgroup solves.
 #include <hip/hip_runtime.h>
@@ -214,7 +216,8 @@ __global__ __launch_bounds__(LEAF_THREADS) void lu_leaf_kernel(float *__restrict
                 bi = i;
             }
         }
-        const uint64_t key = wave_max_key(best >= 0.0f ? pivot_key(best, t + bi * LEAF_THREADS) : 0);
+        const uint64_t key =
+            wave_max_key(best >= 0.0f ? pivot_key(best, t + bi * LEAF_THREADS) : 0);
         if (key != 0) {  // uniform
             const int r = (int)(0xFFFFFFFFu - (uint32_t)key);
             if (lane == (r & 63)) {
@@ -234,8 +237,9 @@ __global__ __launch_bounds__(LEAF_THREADS) void lu_leaf_kernel(float *__restrict
         }
         __syncthreads();
         const uint64_t g0 = gkey[b3];
-        const uint64_t g = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(g0 >> 32)) << 32) |
-                           (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)g0);
+        const uint32_t ghi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(g0 >> 32));
+        const uint32_t glo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)g0);
+        const uint64_t g = ((uint64_t)ghi << 32) | glo;
         if (t == 0) gkey[(j + 2) % 3] = 0;  // last read before this column's barrier
         const int idx = g == 0 ? -1 : (int)(0xFFFFFFFFu - (uint32_t)g);
         const float pivot_mag = g == 0 ? -1.0f : __uint_as_float((uint32_t)(g >> 32));
@@ -461,7 +465,8 @@ __global__ __launch_bounds__(SWAP_THREADS) void laswp_kernel(
 {
     const int t = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if ((int64_t)blockIdx.x < main_blocks) {
-        const int64_t cbase = ((int64_t)blockIdx.x * (SWAP_THREADS / 64) + wave) * SWAP_COLS_PER_WAVE;
+        const int64_t cbase =
+            ((int64_t)blockIdx.x * (SWAP_THREADS / 64) + wave) * SWAP_COLS_PER_WAVE;
         if (cbase >= ncols) return;  // whole wavefront past the last column
         laswp_wave(C, ldc, nrows, ncols, gap0, gapw, ipiv, k0, k1, cbase, t);
     } else {
