@@ -90,6 +90,42 @@ def test_lu_exact_data_is_exact():
 
 
 @pytest.mark.parametrize("mode", [0, 1], ids=["fp32", "bf16x3"])
+def test_lu_exact_data_tall_panels(mode):
+    """A = P T at n = 8200 (T upper triangular, power-of-two entries off the
+    diagonal, 256 +- a power of two on it): the first panels are taller than
+    8192 rows (4-column leaves whose pair hands its interchanges to the
+    triangular-solve leaf), the later ones go through the fused leaf pairs,
+    and every pivot is unique.  Partial pivoting then takes at step j the
+    row that holds row j of T, so the pivots follow from P alone, L = I and
+    U = T exactly; the factors are compared bit for bit."""
+    rng = np.random.default_rng(58)
+    n = 8200
+    t = np.triu(np.exp2(rng.integers(-3, 4, (n, n))).astype(np.float32))
+    t *= rng.choice(np.array([-1.0, 1.0], dtype=np.float32), (n, n))
+    t[np.arange(n), np.arange(n)] = 256.0 + np.exp2(rng.integers(-3, 4, n)).astype(np.float32)
+    perm = rng.permutation(n)
+    a = t[perm]  # row r of A is row perm[r] of T
+    del t
+    # the pivots partial pivoting takes: the current position of row j of T
+    pos = np.empty(n, dtype=np.int64)
+    pos[perm] = np.arange(n)
+    at = perm.copy()  # at[r]: the row of T now at position r
+    want = np.empty(n, dtype=np.int64)
+    for j in range(n):
+        p = pos[j]
+        want[j] = p
+        tj, tp = at[j], at[p]
+        at[j], at[p] = tp, tj
+        pos[tp], pos[tj] = j, p
+    lu, ipiv, info = _factor(a, mode)[:3]
+    assert info == 0
+    assert np.array_equal(ipiv, want)
+    u = np.triu(lu)
+    assert np.array_equal(u, np.triu(a[np.argsort(perm)]).astype(np.float64))
+    assert not np.any(np.tril(lu, -1))
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["fp32", "bf16x3"])
 def test_lu_random_backward_error_and_residual(mode):
     """Random uniform[-1,1] matrices (uniform entries, as HPL uses):
     valid pivots, |L| <= 1, ||P A - L U|| small against n eps ||L|| ||U||,
