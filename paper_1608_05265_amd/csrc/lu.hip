@@ -106,11 +106,41 @@ __device__ inline void laswp_wave(float *__restrict__ C, int64_t ldc, int64_t nr
 // column, else divided by the pivot.
 __device__ inline bool scale_by_reciprocal(float piv) { return fabsf(piv) >= FLT_MIN; }
 
+typedef float leaf_f4 __attribute__((ext_vector_type(4)));
+
+// Panel row of register slot i of thread t.  Interleaved (VEC false): rows
+// t, t + LEAF_THREADS, ...; grouped (VEC true, RPT a multiple of 4): slots
+// 4s .. 4s+3 hold the four consecutive rows 4 LEAF_THREADS s + 4t .. + 3, so
+// a wavefront moves 1 KB of a column with one 16-byte access per lane
+// instead of 256 bytes with one 4-byte access.
+template <bool VEC>
+__device__ __forceinline__ int leaf_row(int t, int i)
+{
+    return VEC ? (i >> 2) * (4 * LEAF_THREADS) + 4 * t + (i & 3) : t + i * LEAF_THREADS;
+}
+template <bool VEC>
+__device__ __forceinline__ int leaf_owner(int r)  // the thread that holds panel row r
+{
+    return VEC ? (r % (4 * LEAF_THREADS)) >> 2 : r % LEAF_THREADS;
+}
+template <bool VEC>
+__device__ __forceinline__ int leaf_slot(int r)  // its register slot
+{
+    return VEC ? (r / (4 * LEAF_THREADS)) * 4 + (r & 3) : r / LEAF_THREADS;
+}
+// Slots whose row can lie at or above a panel column j < 8 (every other
+// slot's row is LEAF_THREADS or more rows down).
+template <bool VEC>
+__host__ __device__ constexpr bool leaf_near_top(int i)
+{
+    return VEC ? i < 4 : i == 0;
+}
+
 // Factor the m x w panel P (w <= W, m <= RPT * LEAF_THREADS, leading
 // dimension lda; its top-left element is A(row0, row0)).  Thread t holds
-// rows t, t + LEAF_THREADS, ... of the panel in registers; the rows past m
-// hold NaN, so that they are never a pivot candidate and need no mask (they
-// are not stored).  For each column j: the row of largest magnitude at or
+// its rows of the panel (leaf_row) in registers; the rows past m hold NaN,
+// so that they are never a pivot candidate and need no mask (they are not
+// stored).  VEC needs P 16-byte aligned and lda a multiple of 4.  For each column j: the row of largest magnitude at or
 // below j (first one on ties) is exchanged with row j across the panel,
 // the entries below the diagonal become multipliers, and the outer product
 // is subtracted from the remaining columns.  A zero pivot leaves its column
@@ -127,7 +157,7 @@ __device__ inline bool scale_by_reciprocal(float piv) { return fabsf(piv) >= FLT
 // The row buffers alternate between even and odd columns and the maximum
 // cycles over three slots (one is cleared two columns ahead of its use), so
 // a wave that runs ahead never overwrites what a slower one still reads.
-template <int RPT, int W, bool UPD>
+template <int RPT, int W, bool UPD, bool VEC>
 __global__ __launch_bounds__(LEAF_THREADS) void lu_leaf_kernel(float *__restrict__ P,
                                                               int64_t lda, int m, int w, int wl,
                                                               int64_t *__restrict__ ipiv,
@@ -135,6 +165,8 @@ __global__ __launch_bounds__(LEAF_THREADS) void lu_leaf_kernel(float *__restrict
 {
     static_assert(RPT * W <= LEAF_REGS, "panel does not fit the register budget");
     static_assert(LEAF_THREADS % 64 == 0, "waves own whole 64-row groups of a thread row");
+    static_assert(!VEC || RPT % 4 == 0, "grouped rows come four at a time");
+    static_assert(W <= 8, "rows at or above a panel column lie in the near-top slots");
     __shared__ float wrow[2][LEAF_WAVES][W];   // each wave's candidate row
     __shared__ float jrow[2][W];               // row j before its exchange
     __shared__ unsigned long long gkey[3];     // largest pivot key of the column
@@ -152,10 +184,27 @@ __global__ __launch_bounds__(LEAF_THREADS) void lu_leaf_kernel(float *__restrict
 #pragma unroll
     for (int c = 0; c < W; ++c) {
         const float *pc = P + (int64_t)c * lda;  // uniform column base, 32-bit row offsets
+        if (VEC) {
 #pragma unroll
-        for (int i = 0; i < RPT; ++i) {
-            const uint32_t r = (uint32_t)(t + i * LEAF_THREADS);
-            v[i][c] = r < (uint32_t)m ? (c < w ? pc[r] : 0.0f) : qnan;
+            for (int s4 = 0; s4 < RPT / 4; ++s4) {
+                const int rb = leaf_row<VEC>(t, 4 * s4);
+                leaf_f4 x;
+                if (c < w && rb + 4 <= m) {
+                    x = *reinterpret_cast<const leaf_f4 *>(pc + rb);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        x[e] = rb + e < m ? (c < w ? pc[rb + e] : 0.0f) : qnan;
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e) v[4 * s4 + e][c] = x[e];
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                const uint32_t r = (uint32_t)leaf_row<VEC>(t, i);
+                v[i][c] = r < (uint32_t)m ? (c < w ? pc[r] : 0.0f) : qnan;
+            }
         }
     }
     __syncthreads();  // gkey cleared
@@ -190,13 +239,32 @@ __global__ __launch_bounds__(LEAF_THREADS) void lu_leaf_kernel(float *__restrict
         for (int q = 0; q < W; ++q) {
             if (q < wl) {  // uniform
                 const float *lq = P + (int64_t)(q - wl) * lda;  // column q of A21
+                float a[RPT];
+                if (VEC) {
 #pragma unroll
-                for (int i = 0; i < RPT; ++i) {
-                    const uint32_t r = (uint32_t)(t + i * LEAF_THREADS);
-                    const float a = r < (uint32_t)m ? lq[r] : 0.0f;
+                    for (int s4 = 0; s4 < RPT / 4; ++s4) {
+                        const int rb = leaf_row<VEC>(t, 4 * s4);
+                        leaf_f4 x;
+                        if (rb + 4 <= m) {
+                            x = *reinterpret_cast<const leaf_f4 *>(lq + rb);
+                        } else {
 #pragma unroll
-                    for (int c = 0; c < W; ++c) v[i][c] -= a * su[q][c];
+                            for (int e = 0; e < 4; ++e) x[e] = rb + e < m ? lq[rb + e] : 0.0f;
+                        }
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) a[4 * s4 + e] = x[e];
+                    }
+                } else {
+#pragma unroll
+                    for (int i = 0; i < RPT; ++i) {
+                        const uint32_t r = (uint32_t)leaf_row<VEC>(t, i);
+                        a[i] = r < (uint32_t)m ? lq[r] : 0.0f;
+                    }
                 }
+#pragma unroll
+                for (int i = 0; i < RPT; ++i)
+#pragma unroll
+                    for (int c = 0; c < W; ++c) v[i][c] -= a[i] * su[q][c];
             }
         }
     }
@@ -210,18 +278,19 @@ __global__ __launch_bounds__(LEAF_THREADS) void lu_leaf_kernel(float *__restrict
         int bi = 0;
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
-            const float a = (i == 0 && t < j) ? -1.0f : fabsf(v[i][j]);
+            const float a = (leaf_near_top<VEC>(i) && leaf_row<VEC>(t, i) < j) ? -1.0f
+                                                                             : fabsf(v[i][j]);
             if (a > best) {
                 best = a;
                 bi = i;
             }
         }
         const uint64_t key =
-            wave_max_key(best >= 0.0f ? pivot_key(best, t + bi * LEAF_THREADS) : 0);
+            wave_max_key(best >= 0.0f ? pivot_key(best, leaf_row<VEC>(t, bi)) : 0);
         if (key != 0) {  // uniform
             const int r = (int)(0xFFFFFFFFu - (uint32_t)key);
-            if (lane == (r & 63)) {
-                const int ri = r / LEAF_THREADS;
+            if (lane == (leaf_owner<VEC>(r) & 63)) {
+                const int ri = leaf_slot<VEC>(r);
 #pragma unroll
                 for (int i = 0; i < RPT; ++i)
                     if (i == ri) {
@@ -231,9 +300,9 @@ __global__ __launch_bounds__(LEAF_THREADS) void lu_leaf_kernel(float *__restrict
                 atomicMax(&gkey[b3], (unsigned long long)key);
             }
         }
-        if (t == j) {
+        if (t == leaf_owner<VEC>(j)) {
 #pragma unroll
-            for (int c = 0; c < W; ++c) jrow[b2][c] = v[0][c];
+            for (int c = 0; c < W; ++c) jrow[b2][c] = v[leaf_slot<VEC>(j)][c];
         }
         __syncthreads();
         const uint64_t g0 = gkey[b3];
@@ -244,16 +313,16 @@ __global__ __launch_bounds__(LEAF_THREADS) void lu_leaf_kernel(float *__restrict
         const int idx = g == 0 ? -1 : (int)(0xFFFFFFFFu - (uint32_t)g);
         const float pivot_mag = g == 0 ? -1.0f : __uint_as_float((uint32_t)(g >> 32));
         const int p = idx >= 0 ? idx : j;
-        const int pt = p % LEAF_THREADS, pi = p / LEAF_THREADS;
+        const int pt = leaf_owner<VEC>(p), pi = leaf_slot<VEC>(p);
         if (t == 0) ipiv[row0 + j] = row0 + p;
         // the pivot row, the new row j (row j itself when nothing qualifies)
         float u[W];
 #pragma unroll
         for (int c = 0; c < W; ++c) u[c] = g != 0 ? wrow[b2][pt >> 6][c] : jrow[b2][c];
         if (p != j) {
-            if (t == j) {
+            if (t == leaf_owner<VEC>(j)) {
 #pragma unroll
-                for (int c = 0; c < W; ++c) v[0][c] = u[c];
+                for (int c = 0; c < W; ++c) v[leaf_slot<VEC>(j)][c] = u[c];
             }
             if (t == pt) {
 #pragma unroll
@@ -275,17 +344,20 @@ __global__ __launch_bounds__(LEAF_THREADS) void lu_leaf_kernel(float *__restrict
 #pragma unroll
                 for (int i = 0; i < RPT; ++i) l[i] = v[i][j] / piv;
             }
-            // the thread's first row is the only one that can lie at or
-            // above row j (rows i >= 1 are LEAF_THREADS or more further down)
-            const bool below = t > j;
-            v[0][j] = below ? l[0] : v[0][j];
+            // only the near-top slots can hold a row at or above row j
 #pragma unroll
-            for (int c = j + 1; c < W; ++c) v[0][c] = below ? v[0][c] - l[0] * u[c] : v[0][c];
+            for (int i = 0; i < RPT; ++i) {
+                if (leaf_near_top<VEC>(i)) {
+                    const bool below = leaf_row<VEC>(t, i) > j;
+                    v[i][j] = below ? l[i] : v[i][j];
 #pragma unroll
-            for (int i = 1; i < RPT; ++i) {
-                v[i][j] = l[i];
+                    for (int c = j + 1; c < W; ++c)
+                        v[i][c] = below ? v[i][c] - l[i] * u[c] : v[i][c];
+                } else {
+                    v[i][j] = l[i];
 #pragma unroll
-                for (int c = j + 1; c < W; ++c) v[i][c] -= l[i] * u[c];
+                    for (int c = j + 1; c < W; ++c) v[i][c] -= l[i] * u[c];
+                }
             }
         } else if (t == 0 && *info == 0) {
             *info = (int)(row0 + j + 1);
@@ -294,10 +366,27 @@ __global__ __launch_bounds__(LEAF_THREADS) void lu_leaf_kernel(float *__restrict
 #pragma unroll
     for (int c = 0; c < W; ++c) {
         float *pc = P + (int64_t)c * lda;
+        if (VEC) {
 #pragma unroll
-        for (int i = 0; i < RPT; ++i) {
-            const uint32_t r = (uint32_t)(t + i * LEAF_THREADS);
-            if (r < (uint32_t)m && c < w) pc[r] = v[i][c];
+            for (int s4 = 0; s4 < RPT / 4; ++s4) {
+                const int rb = leaf_row<VEC>(t, 4 * s4);
+                if (c < w && rb + 4 <= m) {
+                    leaf_f4 x;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) x[e] = v[4 * s4 + e][c];
+                    *reinterpret_cast<leaf_f4 *>(pc + rb) = x;
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (c < w && rb + e < m) pc[rb + e] = v[4 * s4 + e][c];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                const uint32_t r = (uint32_t)leaf_row<VEC>(t, i);
+                if (r < (uint32_t)m && c < w) pc[r] = v[i][c];
+            }
         }
     }
 }
@@ -766,17 +855,27 @@ int64_t leaf_width(int64_t m)
 int leaf(const Lu &c, float *P, int64_t m, int w, int64_t j0, int wl)
 {
     const dim3 grid(1), block(LEAF_THREADS);
-#define MISGEMM_LEAF(R, W, U)                                                                   \
-    hipLaunchKernelGGL((lu_leaf_kernel<R, W, U>), grid, block, 0, c.s, P, c.lda, (int)m, w, wl, \
-                       c.ipiv, j0, c.info)
+#define MISGEMM_LEAF(R, W, U, V)                                                           \
+    hipLaunchKernelGGL((lu_leaf_kernel<R, W, U, V>), grid, block, 0, c.s, P, c.lda, (int)m, w, \
+                       wl, c.ipiv, j0, c.info)
     const int rpt = leaf_rpt(m);
     if (wl > 0 && (rpt == 0 || rpt > LEAF_UPD_RPT)) return MISGEMM_E_BAD_CONFIG;
+    // four consecutive rows per 16-byte access where the panel's columns
+    // are 16-byte aligned and a thread holds 8 or more rows (at 4 rows per
+    // thread the grouped leaf measured slower)
+    const bool vec = c.lda % 4 == 0 && (reinterpret_cast<uintptr_t>(P) & 15) == 0;
     switch (rpt) {
-    case 1: if (wl > 0) MISGEMM_LEAF(1, PANEL_LEAF, true); else MISGEMM_LEAF(1, PANEL_LEAF, false); break;
-    case 2: if (wl > 0) MISGEMM_LEAF(2, PANEL_LEAF, true); else MISGEMM_LEAF(2, PANEL_LEAF, false); break;
-    case 4: if (wl > 0) MISGEMM_LEAF(4, PANEL_LEAF, true); else MISGEMM_LEAF(4, PANEL_LEAF, false); break;
-    case 8: if (wl > 0) MISGEMM_LEAF(8, PANEL_LEAF, true); else MISGEMM_LEAF(8, PANEL_LEAF, false); break;
-    case 16: MISGEMM_LEAF(16, LEAF_REGS / 16, false); break;
+    case 1: if (wl > 0) MISGEMM_LEAF(1, PANEL_LEAF, true, false); else MISGEMM_LEAF(1, PANEL_LEAF, false, false); break;
+    case 2: if (wl > 0) MISGEMM_LEAF(2, PANEL_LEAF, true, false); else MISGEMM_LEAF(2, PANEL_LEAF, false, false); break;
+    case 4: if (wl > 0) MISGEMM_LEAF(4, PANEL_LEAF, true, false); else MISGEMM_LEAF(4, PANEL_LEAF, false, false); break;
+    case 8:
+        if (vec) { if (wl > 0) MISGEMM_LEAF(8, PANEL_LEAF, true, true); else MISGEMM_LEAF(8, PANEL_LEAF, false, true); }
+        else { if (wl > 0) MISGEMM_LEAF(8, PANEL_LEAF, true, false); else MISGEMM_LEAF(8, PANEL_LEAF, false, false); }
+        break;
+    case 16:
+        if (vec) MISGEMM_LEAF(16, LEAF_REGS / 16, false, true);
+        else MISGEMM_LEAF(16, LEAF_REGS / 16, false, false);
+        break;
     default:
         hipLaunchKernelGGL(lu_leaf_tall_kernel, grid, block, 0, c.s, P, c.lda, m, w, c.ipiv, j0,
                            c.info);
