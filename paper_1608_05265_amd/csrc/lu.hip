@@ -701,11 +701,36 @@ __global__ __launch_bounds__(TRSV_ROWS) void trsv_block_kernel(const float *__re
                     if (lane > q) x -= tv[q] * xq;
                 }
             } else {
+                // Each row's quotient by its diagonal entry: where every
+                // diagonal entry of the block is a normal number, through
+                // its reciprocal (computed before the dependent chain) and
+                // one correction step, q0 = x d', x = q0 + (x - q0 d) d'
+                // with both updates fused (correctly rounded for a correctly
+                // rounded d', so exact wherever the quotient is
+                // representable); otherwise by division, so that a zero or
+                // non-finite diagonal gives what x / d gives.
+                float dg = 1.0f;
 #pragma unroll
-                for (int q = 63; q >= 0; --q) {
-                    if (lane == q && live) x = x / tv[q];
-                    const float xq = lane_value(x, q);
-                    if (lane < q) x -= tv[q] * xq;
+                for (int q = 0; q < 64; ++q) dg = q == lane ? tv[q] : dg;
+                const bool normal = !live || (fabsf(dg) >= FLT_MIN && fabsf(dg) <= FLT_MAX);
+                if (__all(normal)) {
+                    const float rdg = 1.0f / dg;
+#pragma unroll
+                    for (int q = 63; q >= 0; --q) {
+                        if (lane == q && live) {
+                            const float q0 = x * rdg;
+                            x = fmaf(fmaf(-q0, dg, x), rdg, q0);
+                        }
+                        const float xq = lane_value(x, q);
+                        if (lane < q) x -= tv[q] * xq;
+                    }
+                } else {
+#pragma unroll
+                    for (int q = 63; q >= 0; --q) {
+                        if (lane == q && live) x = x / tv[q];
+                        const float xq = lane_value(x, q);
+                        if (lane < q) x -= tv[q] * xq;
+                    }
                 }
             }
             xs[r] = x;
