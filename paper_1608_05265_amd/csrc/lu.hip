@@ -34,7 +34,7 @@ constexpr int PANEL_LEAF = 8;       // columns of a leaf panel
 constexpr int LEAF_THREADS = 1024;  // threads of the leaf-panel workgroup
 constexpr int LEAF_WAVES = LEAF_THREADS / 64;
 constexpr int LEAF_REGS = 64;       // panel values one thread holds
-constexpr int LEAF_UPD_RPT = 8;     // tallest leaf (rows per thread) that fuses its sibling's update
+constexpr int LEAF_UPD_RPT = 16;    // tallest leaf (rows per thread) that fuses its sibling's update
 constexpr int SWAP_BLOCK = 32;      // interchanges composed into one permutation
 constexpr int SWAP_THREADS = 256;   // laswp workgroup: four wavefronts
 constexpr int SWAP_COLS_PER_WAVE = 16;
@@ -898,8 +898,8 @@ int leaf(const Lu &c, float *P, int64_t m, int w, int64_t j0, int wl)
         else { if (wl > 0) MISGEMM_LEAF(8, PANEL_LEAF, true, false); else MISGEMM_LEAF(8, PANEL_LEAF, false, false); }
         break;
     case 16:
-        if (vec) MISGEMM_LEAF(16, LEAF_REGS / 16, false, true);
-        else MISGEMM_LEAF(16, LEAF_REGS / 16, false, false);
+        if (vec) { if (wl > 0) MISGEMM_LEAF(16, LEAF_REGS / 16, true, true); else MISGEMM_LEAF(16, LEAF_REGS / 16, false, true); }
+        else { if (wl > 0) MISGEMM_LEAF(16, LEAF_REGS / 16, true, false); else MISGEMM_LEAF(16, LEAF_REGS / 16, false, false); }
         break;
     default:
         hipLaunchKernelGGL(lu_leaf_tall_kernel, grid, block, 0, c.s, P, c.lda, m, w, c.ipiv, j0,

@@ -90,16 +90,19 @@ def test_lu_exact_data_is_exact():
 
 
 @pytest.mark.parametrize("mode", [0, 1], ids=["fp32", "bf16x3"])
-def test_lu_exact_data_tall_panels(mode):
-    """A = P T at n = 8200 (T upper triangular, power-of-two entries off the
-    diagonal, 256 +- a power of two on it): the first panels are taller than
-    8192 rows (4-column leaves whose pair hands its interchanges to the
-    triangular-solve leaf), the later ones go through the fused leaf pairs,
-    and every pivot is unique.  Partial pivoting then takes at step j the
-    row that holds row j of T, so the pivots follow from P alone, L = I and
-    U = T exactly; the factors are compared bit for bit."""
+@pytest.mark.parametrize("lda", [8232, 8235], ids=["lda8232", "lda8235"])
+def test_lu_exact_data_tall_panels(mode, lda):
+    """A = P T at n = 8232 (T upper triangular, power-of-two entries off the
+    diagonal, 256 +- a power of two on it): the first five leaf pairs are
+    taller than 8192 rows (4-column leaves, 16 rows per thread, the right
+    one taking its sibling's update), the later ones hold at most 8 rows
+    per thread, and every pivot is unique; lda 8232 takes the leaves' 16-byte
+    row groups, lda 8235 their one-row accesses.  Partial pivoting then
+    takes at step j the row that holds row j of T, so the pivots follow
+    from P alone, L = I and U = T exactly; the factors are compared bit for
+    bit."""
     rng = np.random.default_rng(58)
-    n = 8200
+    n = 8232
     t = np.triu(np.exp2(rng.integers(-3, 4, (n, n))).astype(np.float32))
     t *= rng.choice(np.array([-1.0, 1.0], dtype=np.float32), (n, n))
     t[np.arange(n), np.arange(n)] = 256.0 + np.exp2(rng.integers(-3, 4, n)).astype(np.float32)
@@ -117,7 +120,7 @@ def test_lu_exact_data_tall_panels(mode):
         tj, tp = at[j], at[p]
         at[j], at[p] = tp, tj
         pos[tp], pos[tj] = j, p
-    lu, ipiv, info = _factor(a, mode)[:3]
+    lu, ipiv, info = _factor(a, mode, lda)[:3]
     assert info == 0
     assert np.array_equal(ipiv, want)
     u = np.triu(lu)
@@ -128,8 +131,9 @@ def test_lu_exact_data_tall_panels(mode):
 @pytest.mark.parametrize("mode", [0, 1], ids=["fp32", "bf16x3"])
 def test_lu_random_backward_error_and_residual(mode):
     """Random uniform[-1,1] matrices (uniform entries, as HPL uses):
-    valid pivots, |L| <= 1, ||P A - L U|| small against n eps ||L|| ||U||,
-    and the solve passes HPL's check (scaled residual < 16 with FP32 eps)."""
+    valid pivots, |L| <= 1, ||P A - L U|| small against n eps ||L|| ||U||
+    and each entry within 4 n eps (|L| |U|)_ij, and the solve passes HPL's
+    check (scaled residual < 16 with FP32 eps)."""
     rng = np.random.default_rng(52)
     for n in (200, 1000, 2048):
         a = rng.uniform(-1, 1, (n, n)).astype(np.float32)
@@ -139,15 +143,49 @@ def test_lu_random_backward_error_and_residual(mode):
         L = np.tril(lu, -1) + np.eye(n)
         U = np.triu(lu)
         assert np.max(np.abs(L)) <= 1.0 + 1e-6
-        err = np.max(np.abs(_permuted(a, ipiv) - L @ U))
+        resid = np.abs(_permuted(a, ipiv) - L @ U)
+        err = np.max(resid)
         bound = 4 * n * EPS32 * np.max(np.sum(np.abs(L), 1)) * np.max(np.sum(np.abs(U), 0))
         assert err <= bound, (n, err, bound)
+        # entry by entry: gamma_n (|L| |U|)_ij, gamma_n about n eps (4 n eps here)
+        assert np.all(resid <= 4 * n * EPS32 * (np.abs(L) @ np.abs(U))), n
         if n == 200:
             continue  # padded lda: solve takes ld = n
         b = rng.uniform(-1, 1, n)
         x = _solve(A, dpiv, n, b.astype(np.float32), mode)
         r = oracle.hpl_scaled_residual(a, x, b.astype(np.float32), EPS32)
         assert r < 16.0, (n, r)
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["fp32", "bf16x3"])
+@pytest.mark.parametrize("lda", [8232, 8235], ids=["lda8232", "lda8235"])
+def test_lu_random_tall_leaf_pairs(mode, lda):
+    """Uniform[-1,1] at n = 8232, so that the first five leaf pairs are
+    taller than 8192 rows (16 rows per thread, the right leaf applying its
+    sibling's solve and update in registers) with both panel layouts (lda
+    8232: 16-byte row groups; 8235: one row per access): valid pivots,
+    |L| <= 1, and every entry of P A - L U on 300 rows (the first 40, whose
+    columns those pairs factor, and 260 drawn at random) within the
+    componentwise backward-error bound of LU in floating point,
+    gamma_n (|L| |U|)_ij with gamma_n about n eps, here 4 n eps (FP32's eps;
+    the bf16x3 products' dropped terms add a few eps per product)."""
+    rng = np.random.default_rng(59)
+    n = 8232
+    a = rng.uniform(-1, 1, (n, n)).astype(np.float32)
+    lu, ipiv, info = _factor(a, mode, lda)[:3]
+    assert info == 0
+    assert np.all(ipiv >= np.arange(n)) and np.all(ipiv < n)
+    L = np.tril(lu, -1)
+    L[np.arange(n), np.arange(n)] = 1.0
+    U = np.triu(lu)
+    del lu
+    assert np.max(np.abs(L)) <= 1.0 + 1e-6
+    rows = np.concatenate([np.arange(40), rng.choice(np.arange(40, n), 260, replace=False)])
+    pa = _permuted(a, ipiv)[rows]
+    err = np.abs(pa - L[rows] @ U)
+    bound = 4 * n * EPS32 * (np.abs(L[rows]) @ np.abs(U))
+    worst = np.unravel_index(np.argmax(err - bound), err.shape)
+    assert np.all(err <= bound), (rows[worst[0]], worst[1], err[worst], bound[worst])
 
 
 def test_lu_singular_and_errors():
