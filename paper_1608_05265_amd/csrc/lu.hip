@@ -57,16 +57,16 @@ __device__ inline uint64_t pivot_key(float mag, int row)
     return ((uint64_t)__float_as_uint(mag) << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)row);
 }
 
-__device__ inline uint64_t umax64(uint64_t a, uint64_t b) { return a > b ? a : b; }
-
 // v from another lane of the same 16-lane row (DPP control CTRL).
 template <int CTRL>
-__device__ inline uint64_t dpp64(uint64_t v)
+__device__ inline uint32_t dpp32(uint32_t v)
 {
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, 0xF, 0xF, true);
-    const uint32_t hi =
-        (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTRL, 0xF, 0xF, true);
-    return ((uint64_t)hi << 32) | lo;
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, true);
+}
+
+__device__ inline uint32_t readlane32(uint32_t v, int lane)
+{
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
 }
 
 __device__ inline uint64_t readlane64(uint64_t v, int lane)
@@ -76,24 +76,34 @@ __device__ inline uint64_t readlane64(uint64_t v, int lane)
     return ((uint64_t)hi << 32) | lo;
 }
 
-// Maximum over each 16-lane row, left in every lane of the row: exchange
-// with the neighbour (quad_perm 1,0,3,2), the other pair (quad_perm
-// 2,3,0,1), the mirrored quad in the half row, the mirrored half row.
-__device__ inline uint64_t row_max_key(uint64_t k)
+// Maximum (MIN false) or minimum (MIN true) over the wavefront (all lanes
+// active), uniform: within each 16-lane row exchange with the neighbour
+// (quad_perm 1,0,3,2), the other pair (quad_perm 2,3,0,1), the mirrored
+// quad in the half row and the mirrored half row; then the four rows
+// through scalar readlanes.
+template <bool MIN>
+__device__ inline uint32_t wave_reduce_u32(uint32_t v)
 {
-    k = umax64(k, dpp64<0xB1>(k));
-    k = umax64(k, dpp64<0x4E>(k));
-    k = umax64(k, dpp64<0x141>(k));
-    k = umax64(k, dpp64<0x140>(k));
-    return k;
+    const auto op = [](uint32_t a, uint32_t b) { return MIN ? (a < b ? a : b) : (a > b ? a : b); };
+    v = op(v, dpp32<0xB1>(v));
+    v = op(v, dpp32<0x4E>(v));
+    v = op(v, dpp32<0x141>(v));
+    v = op(v, dpp32<0x140>(v));
+    return op(op(readlane32(v, 0), readlane32(v, 16)), op(readlane32(v, 32), readlane32(v, 48)));
 }
 
-// Maximum over the wavefront (all lanes active), uniform.
-__device__ inline uint64_t wave_max_key(uint64_t k)
+// The wavefront's largest pivot key (uniform; 0 when no lane has a
+// candidate): from each lane's best magnitude (negative: none) and its row,
+// the largest magnitude first, then the smallest row among the lanes that
+// hold it -- the same key as the maximum of the lanes' pivot keys, in two
+// 32-bit reductions instead of one over 64-bit keys.
+__device__ inline uint64_t wave_pivot_key(float best, int row)
 {
-    k = row_max_key(k);
-    return umax64(umax64(readlane64(k, 0), readlane64(k, 16)),
-                  umax64(readlane64(k, 32), readlane64(k, 48)));
+    const uint32_t u = best >= 0.0f ? __float_as_uint(best) + 1u : 0u;
+    const uint32_t umax = wave_reduce_u32<false>(u);
+    if (umax == 0) return 0;
+    const uint32_t rmin = wave_reduce_u32<true>(u == umax ? (uint32_t)row : 0xFFFFFFFFu);
+    return pivot_key(__uint_as_float(umax - 1u), (int)rmin);
 }
 
 __device__ inline void laswp_wave(float *__restrict__ C, int64_t ldc, int64_t nrows, int64_t ncols,
@@ -285,8 +295,7 @@ __global__ __launch_bounds__(LEAF_THREADS) void lu_leaf_kernel(float *__restrict
                 bi = i;
             }
         }
-        const uint64_t key =
-            wave_max_key(best >= 0.0f ? pivot_key(best, leaf_row<VEC>(t, bi)) : 0);
+        const uint64_t key = wave_pivot_key(best, leaf_row<VEC>(t, bi));
         if (key != 0) {  // uniform
             const int r = (int)(0xFFFFFFFFu - (uint32_t)key);
             if (lane == (leaf_owner<VEC>(r) & 63)) {
