@@ -946,7 +946,8 @@ int getrf(const Lu &c, int64_t j0, int64_t w)
     }
     if (w1 <= lw && w2 <= leaf_width(m2) && w1 <= LEAF) {
         // both halves are leaves, too tall for the right one to take the
-        // node's update: the triangular solve applies the left leaf's
+        // node's update (over LEAF_UPD_RPT * LEAF_THREADS rows, where the
+        // in-memory leaf factors them): the triangular solve applies the left leaf's
         // interchanges to the right half's columns before solving, and one
         // launch after the pair takes the node's interchanges to every
         // other column and the right leaf's to the left one (as above)
