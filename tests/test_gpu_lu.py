@@ -93,10 +93,10 @@ def test_lu_exact_data_is_exact():
 @pytest.mark.parametrize("lda", [8232, 8235], ids=["lda8232", "lda8235"])
 def test_lu_exact_data_tall_panels(mode, lda):
     """A = P T at n = 8232 (T upper triangular, power-of-two entries off the
-    diagonal, 256 +- a power of two on it): the first five leaf pairs are
-    taller than 8192 rows (4-column leaves, 16 rows per thread, the right
-    one taking its sibling's update), the later ones hold at most 8 rows
-    per thread, and every pivot is unique; lda 8232 takes the leaves' 16-byte
+    diagonal, 256 +- a power of two on it): the leaves of the first 36
+    columns are taller than 8192 rows (4 columns, 16 rows per thread; four
+    fused pairs, whose right leaf takes its sibling's update), the later ones
+    hold at most 8 rows per thread, and every pivot is unique; lda 8232 takes the leaves' 16-byte
     row groups, lda 8235 their one-row accesses.  Partial pivoting then
     takes at step j the row that holds row j of T, so the pivots follow
     from P alone, L = I and U = T exactly; the factors are compared bit for
@@ -160,9 +160,10 @@ def test_lu_random_backward_error_and_residual(mode):
 @pytest.mark.parametrize("mode", [0, 1], ids=["fp32", "bf16x3"])
 @pytest.mark.parametrize("lda", [8232, 8235], ids=["lda8232", "lda8235"])
 def test_lu_random_tall_leaf_pairs(mode, lda):
-    """Uniform[-1,1] at n = 8232, so that the first five leaf pairs are
-    taller than 8192 rows (16 rows per thread, the right leaf applying its
-    sibling's solve and update in registers) with both panel layouts (lda
+    """Uniform[-1,1] at n = 8232, so that the leaves of the first 36 columns
+    are taller than 8192 rows (16 rows per thread; four fused pairs, the
+    right leaf applying its sibling's solve and update in registers) with
+    both panel layouts (lda
     8232: 16-byte row groups; 8235: one row per access): valid pivots,
     |L| <= 1, and every entry of P A - L U on 300 rows (the first 40, whose
     columns those pairs factor, and 260 drawn at random) within the
