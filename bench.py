@@ -267,14 +267,18 @@ class Resident:
     through misgemm_sgemm; split-form calls through misgemm_sgemm_ws with a
     workspace this program owns (allocated before any timing, shared by the
     problems, which run one after another on one stream), so that the
-    tuning table's packed configurations can serve them."""
+    tuning table's packed configurations can serve them -- unless `ws` is
+    False: then through misgemm_sgemm too, for shapes whose tuned entry is a
+    split-K configuration (misgemm_sgemm_ws never splits K; misgemm_sgemm
+    keeps the partial tiles in the library's scratch)."""
 
     workspace = None
 
-    def __init__(self, p, dev):
+    def __init__(self, p, dev, ws=True):
         import torch
         import paper_1608_05265_amd as mg
         self.p = p
+        self.ws = ws
         self.A = torch.from_numpy(p.A).to(dev)
         self.B = torch.from_numpy(p.B).to(dev)
         self.C0 = torch.from_numpy(p.C0).to(dev)
@@ -288,7 +292,7 @@ class Resident:
 
     def call(self, mg, mode):
         p = self.p
-        if mode == mg.BF16X3:
+        if mode == mg.BF16X3 and self.ws:
             ws = Resident.workspace
             mg.sgemm_ws(p.transa, p.transb, p.m, p.n, p.k, p.alpha, self.A, p.lda, self.B,
                         p.ldb, p.beta, self.C, p.ldc, mode, ws, ws.numel() * 4)
@@ -1112,7 +1116,10 @@ def main():
                           "measured": measure_peaks(torch)}))
         return
     problems, desc = make_problems(args.workload, args.problem)
-    res = [Resident(p, dev) for p in problems]
+    # the split-K regime's tuned entries are split-K configurations in both
+    # forms, which misgemm_sgemm runs (misgemm_sgemm_ws never splits K)
+    split_regime = args.workload == "skinny"
+    res = [Resident(p, dev, ws=not split_regime) for p in problems]
     torch.cuda.synchronize()
     flops_step = sum(2.0 * r.p.m * r.p.n * r.p.k for r in res)
     big = max(r.p.m * r.p.n * r.p.k for r in res)
@@ -1174,8 +1181,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "gemms_per_step": len(res),
                    "flops_per_step": flops_step,
-                   "forms": "fp32 (value, misgemm_sgemm), bf16x3 (bf16x3 object, "
-                            "misgemm_sgemm_ws with a caller-owned workspace)"},
+                   "forms": "fp32 (value, misgemm_sgemm), bf16x3 (bf16x3 object, " +
+                            ("misgemm_sgemm, split-K partials in the library scratch)"
+                             if split_regime else
+                             "misgemm_sgemm_ws with a caller-owned workspace)")},
         "pct_of_fp32_peak": round(100.0 * f32["tflops"] / PEAK_FP32, 2),
         "bf16x3": {"value": round(x3["tflops"], 3), "unit": "TFLOP/s (FP32-equivalent, 2MNK)",
                    "ms_per_step": round(x3["ms_per_step"], 4),
