@@ -29,16 +29,19 @@ int trans_of(char t)
 
 // Per-device state: three streams (copies in, compute, copies out), grow-only device buffers
 // for A, B and C, and grow-only pinned host buffers (two for C panels on
-// their way in, two on their way out) through which a C with padding rows
-// travels.  Calls on one device are serialized.
+// their way in, two on their way out, two chunks through which A and B
+// travel).  Calls on one device are serialized.
+constexpr int NPIN = 6;
+constexpr int PIN_UPLOAD = 4;                      // first of the two upload chunks
+constexpr size_t UPLOAD_CHUNK = (size_t)64 << 20;  // bytes per upload chunk
 struct HostState {
     std::mutex mu;
     bool init = false;
     hipStream_t copy = nullptr, comp = nullptr, out = nullptr;  // copies in, compute, copies out
     void *buf[3] = {nullptr, nullptr, nullptr};
     size_t cap[3] = {0, 0, 0};
-    void *pin[4] = {nullptr, nullptr, nullptr, nullptr};
-    size_t pin_cap[4] = {0, 0, 0, 0};
+    void *pin[NPIN] = {};
+    size_t pin_cap[NPIN] = {};
 };
 constexpr int MAX_DEV = 64;
 HostState g_host[MAX_DEV];
@@ -101,6 +104,71 @@ void gather_columns(T *dst, const T *src, int64_t m, int64_t cols, int64_t ld, b
     work(0);
     for (auto &th : pool) th.join();
 }
+
+// bytes from src to dst on several host threads for large copies.
+void parallel_memcpy(char *dst, const char *src, size_t bytes)
+{
+    const int nt = bytes >= ((size_t)8 << 20) ? 8 : 1;
+    const size_t part = (bytes / nt + 4095) / 4096 * 4096;
+    auto work = [&](int t) {
+        const size_t off = std::min(bytes, (size_t)t * part);
+        const size_t len = std::min(part, bytes - off);
+        if (len > 0) memcpy(dst + off, src + off, len);
+    };
+    if (nt == 1) {
+        work(0);
+        return;
+    }
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nt; ++t) pool.emplace_back(work, t);
+    work(0);
+    for (auto &th : pool) th.join();
+}
+
+// The two pinned chunks through which read-only operands travel: host
+// threads copy chunk i of the caller's (pageable) range into chunk buffer
+// i % 2, once the transfer of chunk i-2 out of it has finished, and the DMA
+// engine moves it to the device on the copy stream while the host fills the
+// other buffer (handing pageable memory to the runtime directly moved about
+// 20 GB/s).
+struct Uploader {
+    HostState &h;
+    hipEvent_t done[2] = {nullptr, nullptr};
+    bool used[2] = {false, false};
+    int next = 0;
+    explicit Uploader(HostState &hs) : h(hs) {}
+    ~Uploader()
+    {
+        for (hipEvent_t ev : done)
+            if (ev) (void)hipEventDestroy(ev);
+    }
+    hipError_t init()
+    {
+        hipError_t e = hipSuccess;
+        for (int i = 0; i < 2 && e == hipSuccess; ++i)
+            e = hipEventCreateWithFlags(&done[i], hipEventDisableTiming);
+        return e;
+    }
+    hipError_t put(void *dst, const void *src, size_t bytes)
+    {
+        for (size_t off = 0; off < bytes; off += UPLOAD_CHUNK) {
+            const size_t len = std::min(UPLOAD_CHUNK, bytes - off);
+            const int s = next;
+            next ^= 1;
+            if (used[s]) {
+                const hipError_t e = hipEventSynchronize(done[s]);
+                if (e != hipSuccess) return e;
+            }
+            char *pin = (char *)h.pin[PIN_UPLOAD + s];
+            parallel_memcpy(pin, (const char *)src + off, len);
+            hipError_t e = hipMemcpyAsync((char *)dst + off, pin, len, hipMemcpyHostToDevice, h.copy);
+            if (e == hipSuccess) e = hipEventRecord(done[s], h.copy);
+            if (e != hipSuccess) return e;
+            used[s] = true;
+        }
+        return hipSuccess;
+    }
+};
 
 // Copy the rows x cols column-major block with leading dimension ld
 // between host and device, keeping the same leading dimension on the
@@ -173,12 +241,6 @@ int host_gemm(char transa, char transb, int64_t m, int64_t n, int64_t k, T alpha
     T *a = (T *)dA, *b = (T *)dB, *c = (T *)dC;
 
     hipError_t e = hipSuccess;
-    // A whole; B whole when its stored columns are not C's columns (transb)
-    if (reads_ab) {
-        e = copy_block(a, A, arows, acols, lda, hipMemcpyHostToDevice, h.copy, true);
-        if (e == hipSuccess && tb)
-            e = copy_block(b, B, brows, bcols, ldb, hipMemcpyHostToDevice, h.copy, true);
-    }
     const int64_t nb = panel_width(n);
     const int64_t panels = (n + nb - 1) / nb;
     // C's panels go through pinned buffers, gathered and scattered by host
@@ -199,6 +261,22 @@ int host_gemm(char transa, char transb, int64_t m, int64_t n, int64_t k, T alpha
             (i < 2 ? pin_in[i] : pin_out[i - 2]) = (T *)ptr;
         }
         if (rc != 0) return rc;
+    }
+    // A whole; B whole when its stored columns are not C's columns (transb);
+    // both are only read, so they travel as contiguous ranges (padding rows
+    // included) through the pinned upload chunks
+    Uploader up(h);
+    if (reads_ab) {
+        for (int i = 0; i < 2 && rc == 0; ++i) {
+            void *ptr = nullptr;
+            rc = ensure_pinned(h, PIN_UPLOAD + i, UPLOAD_CHUNK, &ptr);
+        }
+        if (rc != 0) return rc;
+        e = up.init();
+        if (e == hipSuccess)
+            e = up.put(a, A, (size_t)(lda * (acols - 1) + arows) * sizeof(T));
+        if (e == hipSuccess && tb)
+            e = up.put(b, B, (size_t)(ldb * (bcols - 1) + brows) * sizeof(T));
     }
     constexpr int nev = 4;
     hipEvent_t in_done[nev] = {}, out_done[nev] = {}, pin_free[2] = {}, pin_full[2] = {};
@@ -224,8 +302,7 @@ int host_gemm(char transa, char transb, int64_t m, int64_t n, int64_t k, T alpha
         // stage panel p (its own device columns, so no panel waits for
         // another): B columns (transb = N), C columns when beta != 0
         if (reads_ab && !tb)
-            e = copy_block(b + j0 * ldb, B + j0 * ldb, brows, cols, ldb, hipMemcpyHostToDevice,
-                           h.copy, true);
+            e = up.put(b + j0 * ldb, B + j0 * ldb, (size_t)(ldb * (cols - 1) + brows) * sizeof(T));
         if (e == hipSuccess && beta != T(0)) {
             if (staged) {
                 // the pinned buffer's previous transfer (panel p-2) must be done
