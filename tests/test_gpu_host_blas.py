@@ -45,6 +45,22 @@ def test_sgemm_host_against_oracle(mode):
             gu.check_full(p, C, "host %s%s %dx%dx%d mode %d" % (ta, tb, m, n, k, mode))
 
 
+@pytest.mark.parametrize("mode", [0, 1], ids=["fp32", "bf16x3"])
+def test_sgemm_host_operands_over_several_upload_chunks(mode):
+    """Operands larger than the pinned upload chunks (64 MB): op(A) of
+    6003 x 6000 floats (144 MB, three chunks, so that a chunk buffer is
+    refilled after its previous transfer), B whole (transposed) or in four
+    column panels; sampled entries against the oracle, C padding intact."""
+    mg = _mg()
+    m, n, k = 6000, 2100, 6000
+    pairs = wl.TRANS_PAIRS if mode == 0 else [("N", "N"), ("N", "T")]
+    for ti, (ta, tb) in enumerate(pairs):
+        p = wl.make_problem(ta, tb, m, n, k, 1.5, -0.5, 8100 + ti, pad=3)
+        C = p.C0.copy()
+        mg.sgemm_host(ta, tb, m, n, k, p.alpha, p.A, p.lda, p.B, p.ldb, p.beta, C, p.ldc, mode)
+        gu.check_sampled(p, C, count=2048, seed=ti, label="host %s%s mode %d" % (ta, tb, mode))
+
+
 def test_fortran_sgemm_symbol():
     """sgemm_ with by-reference arguments; beta = 0 clears a NaN C."""
     for ta, tb in wl.TRANS_PAIRS:
