@@ -32,6 +32,7 @@ int trans_of(char t)
 // their way in, two on their way out, two chunks through which A and B
 // travel).  Calls on one device are serialized.
 constexpr int NPIN = 6;
+constexpr int HOST_COPY_THREADS = 8;               // host threads per large copy (16 measured no faster)
 constexpr int PIN_UPLOAD = 4;                      // first of the two upload chunks
 constexpr size_t UPLOAD_CHUNK = (size_t)64 << 20;  // bytes per upload chunk
 struct HostState {
@@ -88,7 +89,7 @@ template <class T>
 void gather_columns(T *dst, const T *src, int64_t m, int64_t cols, int64_t ld, bool to_packed)
 {
     const int64_t bytes = m * cols * (int64_t)sizeof(T);
-    const int nt = bytes >= ((int64_t)8 << 20) ? 8 : 1;
+    const int nt = bytes >= ((int64_t)8 << 20) ? HOST_COPY_THREADS : 1;
     auto work = [&](int t) {
         for (int64_t c = t; c < cols; c += nt) {
             if (to_packed) memcpy(dst + c * m, src + c * ld, (size_t)m * sizeof(T));
@@ -108,7 +109,7 @@ void gather_columns(T *dst, const T *src, int64_t m, int64_t cols, int64_t ld, b
 // bytes from src to dst on several host threads for large copies.
 void parallel_memcpy(char *dst, const char *src, size_t bytes)
 {
-    const int nt = bytes >= ((size_t)8 << 20) ? 8 : 1;
+    const int nt = bytes >= ((size_t)8 << 20) ? HOST_COPY_THREADS : 1;
     const size_t part = (bytes / nt + 4095) / 4096 * 4096;
     auto work = [&](int t) {
         const size_t off = std::min(bytes, (size_t)t * part);
