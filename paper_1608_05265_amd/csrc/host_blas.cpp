@@ -134,6 +134,7 @@ void parallel_memcpy(char *dst, const char *src, size_t bytes)
 // 20 GB/s).
 struct Uploader {
     HostState &h;
+    size_t chunk = 0;  // bytes per chunk (the pinned buffers hold at least this)
     hipEvent_t done[2] = {nullptr, nullptr};
     bool used[2] = {false, false};
     int next = 0;
@@ -152,8 +153,8 @@ struct Uploader {
     }
     hipError_t put(void *dst, const void *src, size_t bytes)
     {
-        for (size_t off = 0; off < bytes; off += UPLOAD_CHUNK) {
-            const size_t len = std::min(UPLOAD_CHUNK, bytes - off);
+        for (size_t off = 0; off < bytes; off += chunk) {
+            const size_t len = std::min(chunk, bytes - off);
             const int s = next;
             next ^= 1;
             if (used[s]) {
@@ -268,9 +269,15 @@ int host_gemm(char transa, char transb, int64_t m, int64_t n, int64_t k, T alpha
     // included) through the pinned upload chunks
     Uploader up(h);
     if (reads_ab) {
+        // chunks of UPLOAD_CHUNK bytes, smaller when the largest single
+        // transfer (A, B whole, or one panel of B) is smaller
+        const size_t a_bytes = (size_t)(lda * (acols - 1) + arows) * sizeof(T);
+        const size_t b_bytes = tb ? (size_t)(ldb * (bcols - 1) + brows) * sizeof(T)
+                                  : (size_t)(ldb * (std::min(nb, n) - 1) + brows) * sizeof(T);
+        up.chunk = std::min(UPLOAD_CHUNK, std::max(a_bytes, b_bytes));
         for (int i = 0; i < 2 && rc == 0; ++i) {
             void *ptr = nullptr;
-            rc = ensure_pinned(h, PIN_UPLOAD + i, UPLOAD_CHUNK, &ptr);
+            rc = ensure_pinned(h, PIN_UPLOAD + i, up.chunk, &ptr);
         }
         if (rc != 0) return rc;
         e = up.init();
